@@ -1,0 +1,132 @@
+"""Physics pins of the oracle: hydrodynamic limits the paper states (Sec. 2.1)
+and the measurements of its numerical tests (Sec. 4).
+
+* shear-wave decay gives the kinematic viscosity nu = c_S^2 (tau - 1/2);
+* with G = 0 an order-parameter wave decays with D = c_S^2 (tau - 1/2), the
+  diffusive part of J^(A);
+* flat interfaces at mechanical equilibrium have equal bulk pressures
+  p = c_S^2 (rho_A + rho_B) + c_S^2 G rho_A rho_B on both sides (checked with
+  tau_A != tau_B so that the two phases are not mirror images);
+* the paper's worked parameter set (tau = 0.55, rho = 1.4, g_AB = 0.164; Sec. 4
+  and Table 2) gives a bulk order parameter phi = rho_A - rho_B close to +-1;
+* static drops obey the Laplace law Delta p = sigma / R (Sec. 4.1).
+"""
+from multiprocessing import Pool
+
+import numpy as np
+import pytest
+
+import oracle
+import sc_inputs
+
+CS2 = 1.0 / 3.0
+
+
+def _amplitude(field, k, axis_coord):
+    return 2.0 * np.mean(field * np.sin(k * axis_coord))
+
+
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("tau", [0.8, 1.2])
+def test_shear_wave_viscosity(q, tau):
+    """G = 0, rho_A = rho_B: u_x = u0 sin(2 pi y / L) decays as exp(-nu k^2 t)."""
+    L = 64
+    shape = (1, L, 1) if q == 9 else (1, L, 1)
+    y = np.arange(L, dtype=float).reshape(1, L, 1)
+    k = 2 * np.pi / L
+    u = np.zeros((3,) + shape)
+    u[0] = 1e-4 * np.sin(k * y)
+    f = oracle.init(q, np.full(shape, 0.5), np.full(shape, 0.5), u)
+    f = oracle.run(f, tau, tau, 0.0, 100)
+    a1 = _amplitude(oracle.observables(f, tau, tau, 0.0)[1][0], k, y)
+    f = oracle.run(f, tau, tau, 0.0, 600)
+    a2 = _amplitude(oracle.observables(f, tau, tau, 0.0)[1][0], k, y)
+    nu_meas = -np.log(a2 / a1) / (600 * k * k)
+    nu = CS2 * (tau - 0.5)
+    assert abs(nu_meas - nu) / nu < 5e-3
+
+
+@pytest.mark.parametrize("tau", [0.7, 1.0])
+def test_interdiffusion_coefficient(tau):
+    """G = 0: phi = eps sin(2 pi x / L) decays with D = c_S^2 (tau - 1/2)."""
+    L = 64
+    x = np.arange(L, dtype=float).reshape(1, 1, L)
+    k = 2 * np.pi / L
+    phi = 1e-4 * np.sin(k * x)
+    f = oracle.init(9, 0.5 + phi / 2, 0.5 - phi / 2)
+    f = oracle.run(f, tau, tau, 0.0, 100)
+    r = oracle.observables(f, tau, tau, 0.0)[0]
+    a1 = _amplitude(r[0] - r[1], k, x)
+    f = oracle.run(f, tau, tau, 0.0, 800)
+    r = oracle.observables(f, tau, tau, 0.0)[0]
+    a2 = _amplitude(r[0] - r[1], k, x)
+    D_meas = -np.log(a2 / a1) / (800 * k * k)
+    D = CS2 * (tau - 0.5)
+    assert abs(D_meas - D) / D < 5e-3
+
+
+@pytest.mark.parametrize("tA,tB,G", [(0.7, 1.2, 1.3), (0.6, 1.4, 1.5)])
+def test_flat_interface_bulk_pressures_balance(tA, tB, G):
+    fl = sc_inputs.flat_interface(64, 1, 1, rho_total=1.05, phi0=0.85)
+    f = oracle.init(9, fl.rho_A, fl.rho_B)
+    f = oracle.run(f, tA, tB, G, 15000)
+    rho, _, p, _ = oracle.observables(f, tA, tB, G)
+    a, b = rho[:, 0, 0, 32], rho[:, 0, 0, 0]
+    assert a[0] > 0.8 and b[1] > 1.0           # phase separated, asymmetric bulks
+    pa = CS2 * a.sum() + CS2 * G * a[0] * a[1]
+    pb = CS2 * b.sum() + CS2 * G * b[0] * b[1]
+    assert abs(p[0, 0, 32] - pa) < 1e-15 and abs(p[0, 0, 0] - pb) < 1e-15
+    assert abs(pa - pb) < 1e-6 * pa
+    # other prefactors of the interaction term would not balance
+    for g2 in (G / 2, 2 * G):
+        qa = CS2 * a.sum() + CS2 * g2 * a[0] * a[1]
+        qb = CS2 * b.sum() + CS2 * g2 * b[0] * b[1]
+        assert abs(qa - qb) > 1e-2 * pa
+
+
+def test_worked_example_bulk_order_parameter():
+    """Sec. 4: tau = 0.55, rho = 1.4, g_AB = 0.164 were chosen so that
+    phi = +-1 in the pure phases (g^(tau) = 1.804).  A flat interface settles at
+    |phi| = 1.045 here, within 5 % of the paper's value; the mean-field root of
+    its mu^(tau) = 0 is 1.0107.  The residual comes from the lattice
+    discreteness of an interface about one site wide and does not vanish as
+    tau -> 1/2 at fixed g^(tau)."""
+    fl = sc_inputs.flat_interface(64, 1, 1, rho_total=1.4, phi0=1.0107)
+    f = oracle.init(9, fl.rho_A, fl.rho_B)
+    f = oracle.run(f, 0.55, 0.55, 0.164, 100000)
+    rho = oracle.observables(f, 0.55, 0.55, 0.164)[0]
+    phi_in = rho[0, 0, 0, 32] - rho[1, 0, 0, 32]
+    phi_out = rho[0, 0, 0, 0] - rho[1, 0, 0, 0]
+    assert abs(phi_in + phi_out) < 1e-8                 # symmetric
+    assert abs(phi_in - 1.0) < 0.05
+    assert abs(rho[0, 0, 0, 32] + rho[1, 0, 0, 32] - 1.4) < 0.01
+
+
+def _laplace_drop(R):
+    L, tau, G = 80, 1.0, 1.3
+    # coexistence densities of a flat interface at these parameters (0.9663 / 0.1022)
+    fl = sc_inputs.drop(L, L, 1, radius=R, rho_in=0.96634, rho_out=0.10221, width=1.0,
+                        noise=0.0)
+    f = oracle.init(9, fl.rho_A, fl.rho_B)
+    f = oracle.run(f, tau, tau, G, 3000)
+    _, _, _, T = oracle.observables(f, tau, tau, G, probe=list(fl.centre) + [R])
+    return T["dp"], T["R_eff"]
+
+
+@pytest.mark.slow
+def test_laplace_law_linearity():
+    """Sec. 4.1: sigma = R (P_i - P_o).  Delta p against 1/R_eff is a line
+    through the origin: r^2 >= 0.999 and an intercept within 2 % of max Delta p."""
+    Rs = [8, 10, 12, 14, 16, 18]
+    with Pool(min(6, len(Rs))) as pool:
+        res = pool.map(_laplace_drop, Rs)
+    dp = np.array([r[0] for r in res])
+    x = 1.0 / np.array([r[1] for r in res])
+    A = np.vstack([x, np.ones_like(x)]).T
+    (sigma, b), *_ = np.linalg.lstsq(A, dp, rcond=None)
+    fit = A @ [sigma, b]
+    r2 = 1 - ((dp - fit) ** 2).sum() / ((dp - dp.mean()) ** 2).sum()
+    assert sigma > 0
+    assert r2 >= 0.999
+    assert abs(b) <= 0.02 * dp.max()
+    assert np.all(np.abs(np.array([r[1] for r in res]) - Rs) < 1.0)
