@@ -1,0 +1,142 @@
+"""Benchmark of the two-component Shan-Chen step on one MI355X.
+
+Workload: D3Q19 two-component Shan-Chen BGK, 256^3 periodic, spinodal
+decomposition from rho_A = rho_B = 0.5 with seeded U(-0.01, 0.01) noise
+(seed 3), G = 1.6, tau_A = tau_B = 1.0.  A step is one full lattice time step
+(moments, force gather, force shift, collision, streaming) of both species.
+
+Prints one JSON line: MLUPS of the FP64 step (value), its HBM roofline
+fraction from algorithmic bytes (2 species x 19 populations x read+write x
+8 B = 608 B per site update) over the step kernel's average duration timed
+with HIP events on the lattice's stream, the FP32-shifted step's figures, a
+streaming-copy ceiling, and the FP64 CPU oracle timed on the host on one step
+of the same lattice.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E
+Q19 = 19
+L = 256
+G, TAU = 1.6, 1.0
+WORKLOAD = ("D3Q19 two-component Shan-Chen BGK 256^3 periodic, spinodal from rho_A=rho_B=0.5 "
+            "+ U(-0.01,0.01) noise (seed 3), G=1.6, tau=1.0")
+
+
+def b_alg(q: int, esize: int) -> int:
+    """Algorithmic bytes per site update: 2 species x Q x (read + write)."""
+    return 2 * q * 2 * esize
+
+
+def time_lattice(fields, precision, steps, warmup, kernel=None):
+    import torch
+    from paper_1112_5547_amd import Lattice
+    lat = Lattice(Q19, L, L, L, tau_A=TAU, tau_B=TAU, G=G, precision=precision)
+    if kernel:
+        lat.set_kernel(*kernel)
+    lat.init(fields.rho_A, fields.rho_B)
+    T0 = lat.totals()
+    lat.step(warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_events = lat.time_steps(steps)     # HIP events on the lattice's stream
+    lat.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    T = lat.totals()
+    kern = lat.kernel
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return {"wall_s": wall, "kernel_ms": ms_events / steps, "T0": T0, "T": T, "kernel": kern}
+
+
+def cpu_baseline(fields):
+    """The FP64 oracle (plain C, one thread) on one step of the same lattice."""
+    import oracle
+    oracle.build(force=False)
+    f0 = oracle.init(Q19, fields.rho_A, fields.rho_B)
+    t0 = time.perf_counter()
+    oracle.run(f0, TAU, TAU, G, 1)
+    dt = time.perf_counter() - t0
+    n = L ** 3
+    return {"value": n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"1 full time step of the 256^3 D3Q19 lattice ({n} site updates, "
+                      f"{dt:.1f} s, single-threaded C oracle, -O2, no FMA contraction)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design, not a built path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import sc_inputs
+    from paper_1112_5547_amd import copy_bench
+
+    torch.cuda.set_device(0)
+    fields = sc_inputs.spinodal(L, L, L, rho0=0.5, noise=0.01, seed=3)
+    n = L ** 3
+
+    r64 = time_lattice(fields, "fp64", args.steps, args.warmup)
+    mlups = n * args.steps / r64["wall_s"] / 1e6
+    ach = b_alg(Q19, 8) * n / (r64["kernel_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS + % HBM roofline, D3Q19 2-comp SC 256^3",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r64["wall_s"] * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "lattice": "D3Q19", "size": [L, L, L],
+                   "precision": "fp64", "kernel": list(r64["kernel"])},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "kernel": "k_step_fused<19,PF64>", "kernel_ms": round(r64["kernel_ms"], 4),
+                     "bytes_per_site": b_alg(Q19, 8)},
+        "checks": {"mass_drift_A": (r64["T"]["mass_A"] - r64["T0"]["mass_A"]) / r64["T0"]["mass_A"],
+                   "mom_x": r64["T"]["mom_x"], "max_u": r64["T"]["max_u"]},
+    }
+    if not args.no_fp32:
+        r32 = time_lattice(fields, "fp32_shifted", args.steps, args.warmup)
+        ach32 = b_alg(Q19, 4) * n / (r32["kernel_ms"] * 1e-3) / 1e9
+        out["fp32_shifted"] = {
+            "value": round(n * args.steps / r32["wall_s"] / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(r32["wall_s"] * 1e3 / args.steps, 4),
+            "roofline": {"bound": "hbm", "achieved": round(ach32, 1), "peak": PEAK_HBM_GBPS,
+                         "unit": "GB/s", "frac": round(ach32 / PEAK_HBM_GBPS, 4),
+                         "kernel_ms": round(r32["kernel_ms"], 4), "bytes_per_site": b_alg(Q19, 4)},
+            "kernel": list(r32["kernel"]),
+            "mass_drift_A": (r32["T"]["mass_A"] - r32["T0"]["mass_A"]) / r32["T0"]["mass_A"],
+        }
+    out["copy_ceiling_GBps"] = round(copy_bench(2 << 30, reps=10), 1)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(fields)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,570 @@
+// sc_batch.hip -- batched execution of many independent Shan-Chen lattices.
+//
+// Three launch forms advance the members of a batch by an epoch of K steps:
+//   PER_LATTICE : one launch per lattice per step (the plain baseline);
+//   FUSED       : one launch per step covering every member's tiles, the K
+//                 launches captured once into a HIP graph and replayed;
+//   PERSISTENT  : one launch per epoch; co-resident blocks claim tiles from a
+//                 per-step counter and meet at a grid barrier between steps.
+// All three run TileStep::run for every tile, so a lattice evolves bitwise
+// the same alone or in any batch.  D2Q9 and D3Q19 members share a launch:
+// D2Q9 tiles are NT x 1, D3Q19 tiles TX19 x TY19 with TX19 * TY19 = NT.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm_sc.h"
+#include "sc_internal.h"
+#include "sc_runtime.h"
+
+using namespace sc;
+
+namespace {
+
+struct BatchDesc {
+    StepParams sp[2];  // parity 0 / 1 (source and destination swapped)
+    int Q;
+    int base_parity;   // buffer holding the state at epoch start
+    int steps;         // steps of this epoch
+    int pad;
+};
+
+struct WorkItem {
+    int member, tile_x, tile_y, chunk;
+};
+
+// sync words: [0] barrier count, [1] barrier generation, [2] timeout flag,
+// [3..3+K) per-step tile claim counters
+constexpr int SYNC_COUNT = 0, SYNC_GEN = 1, SYNC_TIMEOUT = 2, SYNC_CTR = 3;
+constexpr unsigned kSpinLimit = 1u << 26;  // ~seconds of s_sleep polling per barrier
+
+template <class PR, int NT, int TX19, int TY19>
+struct BatchTiles {
+    using T9 = TileStep<9, PR, NT, 1>;
+    using T19 = TileStep<19, PR, TX19, TY19>;
+    static_assert(TX19 * TY19 == NT, "both lattice types use the block size");
+    static constexpr int LDS_ELEMS =
+        T9::LDS_ELEMS > T19::LDS_ELEMS ? T9::LDS_ELEMS : T19::LDS_ELEMS;
+    __device__ static __forceinline__ void run(const BatchDesc& d, const WorkItem& w, int k,
+                               typename PR::A* lds) {
+        const int parity = d.base_parity ^ (k & 1);
+        if (d.Q == 9)
+            T9::run(d.sp[parity], w.tile_x, w.tile_y, w.chunk, lds);
+        else
+            T19::run(d.sp[parity], w.tile_x, w.tile_y, w.chunk, lds);
+    }
+};
+
+template <class PR>
+struct BatchWaves {
+    static constexpr int value = PR::shifted ? 3 : 2;
+};
+
+template <class PR, int NT, int TX19, int TY19>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<PR>::value)))
+k_batch_step(const BatchDesc* __restrict__ desc, const WorkItem* __restrict__ work, int nwork,
+             int k) {
+    using BT = BatchTiles<PR, NT, TX19, TY19>;
+    __shared__ typename PR::A lds[BT::LDS_ELEMS];
+    const int it = (int)blockIdx.x;
+    if (it >= nwork) return;
+    const WorkItem w = work[it];
+    const BatchDesc& d = desc[w.member];
+    if (k >= d.steps) return;
+    BT::run(d, w, k, lds);
+}
+
+__device__ __forceinline__ unsigned ld_acquire(unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide barrier for co-resident blocks; returns false if the wait hit
+// the spin limit or another block already reported a timeout (all blocks
+// then leave the kernel, so every wave terminates).
+__device__ bool grid_barrier(unsigned* sync, unsigned nblocks, unsigned& gen, int* s_flag) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned g = gen;
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&sync[SYNC_COUNT], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&sync[SYNC_COUNT], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sync[SYNC_GEN], g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (ld_acquire(&sync[SYNC_GEN]) == g) {
+                if (ld_acquire(&sync[SYNC_TIMEOUT]) != 0u || ++spins > kSpinLimit) {
+                    __hip_atomic_store(&sync[SYNC_TIMEOUT], 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        gen = g + 1;
+        *s_flag = ok;
+    }
+    __syncthreads();
+    const bool ok = *s_flag != 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
+}
+
+template <class PR, int NT, int TX19, int TY19>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<PR>::value)))
+k_batch_persistent(const BatchDesc* __restrict__ desc, const WorkItem* __restrict__ work,
+                   int nwork, int ksteps, unsigned* sync) {
+    using BT = BatchTiles<PR, NT, TX19, TY19>;
+    __shared__ typename PR::A lds[BT::LDS_ELEMS];
+    __shared__ int s_item;
+    __shared__ int s_flag;
+    unsigned gen = 0;
+    for (int k = 0; k < ksteps; ++k) {
+        for (;;) {
+            if (threadIdx.x == 0)
+                s_item = (int)__hip_atomic_fetch_add(&sync[SYNC_CTR + k], 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const int it = s_item;
+            __syncthreads();
+            if (it >= nwork) break;
+            const WorkItem w = work[it];
+            const BatchDesc& d = desc[w.member];
+            if (k < d.steps) BT::run(d, w, k, lds);
+        }
+        if (k + 1 < ksteps && !grid_barrier(sync, gridDim.x, gen, &s_flag)) return;
+    }
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// --- launch table ------------------------------------------------------------
+
+struct BatchCfg {
+    int nt, tx19, ty19;
+};
+static const BatchCfg kBatchCfgs[] = {{256, 64, 4}, {256, 32, 8}, {256, 16, 16}, {128, 32, 4},
+                                      {512, 64, 8}, {512, 32, 16}};
+
+using StepFn = void (*)(const BatchDesc*, const WorkItem*, int, int);
+using PersFn = void (*)(const BatchDesc*, const WorkItem*, int, int, unsigned*);
+
+template <class PR>
+bool lookup_fns(int nt, int tx19, int ty19, StepFn* sf, PersFn* pf) {
+#define SC_CFG(NT_, X_, Y_)                                          \
+    if (nt == NT_ && tx19 == X_ && ty19 == Y_) {                     \
+        *sf = k_batch_step<PR, NT_, X_, Y_>;                         \
+        *pf = k_batch_persistent<PR, NT_, X_, Y_>;                   \
+        return true;                                                 \
+    }
+    SC_CFG(256, 64, 4)
+    SC_CFG(256, 32, 8)
+    SC_CFG(256, 16, 16)
+    SC_CFG(128, 32, 4)
+    SC_CFG(512, 64, 8)
+    SC_CFG(512, 32, 16)
+#undef SC_CFG
+    return false;
+}
+
+bool cfg_supported(int nt, int tx19, int ty19) {
+    for (const BatchCfg& c : kBatchCfgs)
+        if (c.nt == nt && c.tx19 == tx19 && c.ty19 == ty19) return true;
+    return false;
+}
+
+struct Member {
+    lbm_sc* h;
+    long long remaining;
+};
+
+// One precision group's device tables and cached graph.
+struct Group {
+    BatchDesc* d_desc = nullptr;
+    size_t desc_cap = 0;
+    WorkItem* d_work = nullptr;
+    size_t work_cap = 0;
+    unsigned* d_sync = nullptr;
+    size_t sync_cap = 0;
+    BatchDesc* h_desc = nullptr;  // pinned staging
+    WorkItem* h_work = nullptr;
+    hipEvent_t staged = nullptr;  // last upload from the staging buffers
+    hipGraphExec_t gexec = nullptr;
+    int g_mode = -1, g_nwork = -1, g_k = -1, g_grid = -1;
+};
+
+}  // namespace
+
+struct lbm_batch {
+    size_t budget = 0, used = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    std::vector<Member> members;
+    int nt = 256, tx19 = 64, ty19 = 4;
+    int mb9 = 0, mb19 = 0;  // 0: each member's own march chunk
+    Group grp[2];           // FP64, FP32-shifted
+    int err = 0;
+};
+
+namespace {
+
+#define BCALL(b, expr)                    \
+    do {                                  \
+        hipError_t e_ = (expr);           \
+        if (e_ != hipSuccess) {           \
+            (b)->err = LBM_EDEVICE;       \
+            return LBM_EDEVICE;           \
+        }                                 \
+    } while (0)
+
+void free_group(Group& g) {
+    if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+    if (g.staged) {
+        (void)hipEventSynchronize(g.staged);
+        (void)hipEventDestroy(g.staged);
+    }
+    (void)hipFree(g.d_desc);
+    (void)hipFree(g.d_work);
+    (void)hipFree(g.d_sync);
+    (void)hipHostFree(g.h_desc);
+    (void)hipHostFree(g.h_work);
+    g = Group();
+}
+
+int ensure(lbm_batch* b, Group& g, size_t ndesc, size_t nwork, int ksteps) {
+    if (!g.staged) BCALL(b, hipEventCreateWithFlags(&g.staged, hipEventDisableTiming));
+    // the staging buffers may still feed an upload in flight
+    BCALL(b, hipEventSynchronize(g.staged));
+    if (ndesc > g.desc_cap) {
+        size_t cap = std::max<size_t>(ndesc, 2 * g.desc_cap);
+        (void)hipFree(g.d_desc);
+        (void)hipHostFree(g.h_desc);
+        g.d_desc = nullptr;
+        g.h_desc = nullptr;
+        BCALL(b, hipMalloc(&g.d_desc, cap * sizeof(BatchDesc)));
+        BCALL(b, hipHostMalloc(&g.h_desc, cap * sizeof(BatchDesc), 0));
+        g.desc_cap = cap;
+        if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+        g.gexec = nullptr;
+    }
+    if (nwork > g.work_cap) {
+        size_t cap = std::max<size_t>(nwork, 2 * g.work_cap);
+        (void)hipFree(g.d_work);
+        (void)hipHostFree(g.h_work);
+        g.d_work = nullptr;
+        g.h_work = nullptr;
+        BCALL(b, hipMalloc(&g.d_work, cap * sizeof(WorkItem)));
+        BCALL(b, hipHostMalloc(&g.h_work, cap * sizeof(WorkItem), 0));
+        g.work_cap = cap;
+        if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+        g.gexec = nullptr;
+    }
+    const size_t nsync = SYNC_CTR + (size_t)ksteps;
+    if (nsync > g.sync_cap) {
+        size_t cap = std::max<size_t>(nsync, 2 * g.sync_cap);
+        (void)hipFree(g.d_sync);
+        g.d_sync = nullptr;
+        BCALL(b, hipMalloc(&g.d_sync, cap * sizeof(unsigned)));
+        g.sync_cap = cap;
+        if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+        g.gexec = nullptr;
+    }
+    return LBM_OK;
+}
+
+int member_mb(const lbm_batch* b, const lbm_sc* h) {
+    const int o = h->Q == 9 ? b->mb9 : b->mb19;
+    return o > 0 ? o : h->mb;
+}
+
+// Enqueues one epoch of the members of one precision group.
+int run_group(lbm_batch* b, int prec, const std::vector<int>& idx, const std::vector<int>& ksteps,
+              int K, int mode) {
+    Group& g = b->grp[prec];
+    // descriptors and the work list (largest-cost lattices first)
+    struct Item {
+        WorkItem w;
+        double cost;
+    };
+    std::vector<Item> items;
+    std::vector<BatchDesc> descs(idx.size());
+    for (size_t m = 0; m < idx.size(); ++m) {
+        lbm_sc* h = b->members[idx[m]].h;
+        const int save_tx = h->tx, save_ty = h->ty, save_mb = h->mb;
+        h->tx = h->Q == 9 ? b->nt : b->tx19;
+        h->ty = h->Q == 9 ? 1 : b->ty19;
+        h->mb = member_mb(b, h);
+        BatchDesc& d = descs[m];
+        memset(&d, 0, sizeof(d));
+        d.sp[0] = sc_step_params(h, 0);
+        d.sp[1] = sc_step_params(h, 1);
+        h->tx = save_tx;
+        h->ty = save_ty;
+        h->mb = save_mb;
+        d.Q = h->Q;
+        d.base_parity = h->cur;
+        d.steps = ksteps[m];
+        const StepParams& sp = d.sp[0];
+        const double per = (double)h->Q * (h->Q == 9 ? b->nt : b->tx19 * b->ty19) *
+                           (double)sp.mb;
+        for (int c = 0; c < sp.nchunks; ++c)
+            for (int ty = 0; ty < sp.nty; ++ty)
+                for (int tx = 0; tx < sp.ntx; ++tx) {
+                    const int planes = std::min(sp.mb, sp.NM - c * sp.mb);
+                    items.push_back({{(int)m, tx, ty, c}, per * planes / sp.mb + 1e-9 * m});
+                }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item& a, const Item& c) { return a.cost > c.cost; });
+    const int nwork = (int)items.size();
+    int rc = ensure(b, g, descs.size(), items.size(), K);
+    if (rc) return rc;
+    memcpy(g.h_desc, descs.data(), descs.size() * sizeof(BatchDesc));
+    for (int i = 0; i < nwork; ++i) g.h_work[i] = items[i].w;
+    BCALL(b, hipMemcpyAsync(g.d_desc, g.h_desc, descs.size() * sizeof(BatchDesc),
+                            hipMemcpyHostToDevice, b->stream));
+    BCALL(b, hipMemcpyAsync(g.d_work, g.h_work, (size_t)nwork * sizeof(WorkItem),
+                            hipMemcpyHostToDevice, b->stream));
+    BCALL(b, hipEventRecord(g.staged, b->stream));
+
+    StepFn sf = nullptr;
+    PersFn pf = nullptr;
+    const bool ok = prec == 0 ? lookup_fns<PF64>(b->nt, b->tx19, b->ty19, &sf, &pf)
+                              : lookup_fns<PF32S>(b->nt, b->tx19, b->ty19, &sf, &pf);
+    if (!ok) return LBM_EINVAL;
+
+    int grid = nwork;
+    if (mode == LBM_BATCH_PERSISTENT) {
+        int per_cu = 0, dev = 0;
+        BCALL(b, hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        BCALL(b, hipGetDeviceProperties(&prop, dev));
+        BCALL(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)pf, b->nt, 0));
+        if (per_cu < 1) return LBM_EDEVICE;
+        grid = std::min(nwork, per_cu * prop.multiProcessorCount);
+    }
+    // replay the cached graph when the launch shape is unchanged (the tables
+    // are rewritten in place, so the captured arguments stay valid)
+    if (!(g.gexec && g.g_mode == mode && g.g_nwork == nwork && g.g_k == K && g.g_grid == grid)) {
+        if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+        g.gexec = nullptr;
+        hipGraph_t graph = nullptr;
+        BCALL(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = hipSuccess;
+        if (mode == LBM_BATCH_FUSED) {
+            for (int k = 0; k < K && le == hipSuccess; ++k) {
+                hipLaunchKernelGGL(sf, dim3(nwork), dim3(b->nt), 0, b->stream, g.d_desc, g.d_work,
+                                   nwork, k);
+                le = hipGetLastError();
+            }
+        } else {
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, b->stream, g.d_sync, SYNC_CTR + K);
+            le = hipGetLastError();
+            if (le == hipSuccess) {
+                hipLaunchKernelGGL(pf, dim3(grid), dim3(b->nt), 0, b->stream, g.d_desc, g.d_work,
+                                   nwork, K, g.d_sync);
+                le = hipGetLastError();
+            }
+        }
+        hipError_t ee = hipStreamEndCapture(b->stream, &graph);
+        if (le != hipSuccess || ee != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            b->err = LBM_EDEVICE;
+            return LBM_EDEVICE;
+        }
+        hipError_t ie = hipGraphInstantiate(&g.gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            g.gexec = nullptr;
+            b->err = LBM_EDEVICE;
+            return LBM_EDEVICE;
+        }
+        g.g_mode = mode;
+        g.g_nwork = nwork;
+        g.g_k = K;
+        g.g_grid = grid;
+    }
+    BCALL(b, hipGraphLaunch(g.gexec, b->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(lbm_batch** out, size_t hbm_budget, void* stream) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return LBM_ENOMEM;
+    b->budget = hbm_budget;
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        return LBM_EDEVICE;
+    }
+    if (stream) {
+        b->stream = static_cast<hipStream_t>(stream);
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return LBM_EDEVICE;
+        }
+        b->own_stream = true;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_add(lbm_batch* b, lbm_sc* h, long long steps) {
+    if (!b || !h || steps < 0) return LBM_EINVAL;
+    if (b->err) return b->err;
+    if (h->err) return h->err;
+    if (!h->inited) return LBM_ESTATE;
+    if (h->batch) return LBM_EINVAL;
+    if (b->budget && b->used + h->mem_bytes > b->budget) return LBM_EBUDGET;
+    (void)hipSetDevice(b->device);
+    // the handle's own queued work (initialisation) precedes batch work
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return LBM_EDEVICE;
+    h->batch = b;
+    b->used += h->mem_bytes;
+    b->members.push_back({h, steps});
+    return LBM_OK;
+}
+
+int lbm_batch_remove(lbm_batch* b, lbm_sc* h) {
+    if (!b || !h) return LBM_EINVAL;
+    for (size_t i = 0; i < b->members.size(); ++i)
+        if (b->members[i].h == h) {
+            (void)hipSetDevice(b->device);
+            (void)hipStreamSynchronize(b->stream);
+            h->batch = nullptr;
+            b->used -= h->mem_bytes;
+            b->members.erase(b->members.begin() + i);
+            return LBM_OK;
+        }
+    return LBM_EINVAL;
+}
+
+int lbm_batch_run(lbm_batch* b, int epoch_steps, int mode) {
+    if (!b || epoch_steps < 0) return LBM_EINVAL;
+    if (b->err) return b->err;
+    if (mode != LBM_BATCH_PER_LATTICE && mode != LBM_BATCH_FUSED && mode != LBM_BATCH_PERSISTENT)
+        return LBM_EINVAL;
+    if (epoch_steps == 0) return LBM_OK;
+    (void)hipSetDevice(b->device);
+    std::vector<int> idx[2], ks[2];
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        Member& m = b->members[i];
+        if (m.remaining <= 0 || m.h->err) continue;
+        const int k = (int)std::min<long long>(m.remaining, epoch_steps);
+        const int prec = m.h->p.precision == LBM_FP64 ? 0 : 1;
+        idx[prec].push_back((int)i);
+        ks[prec].push_back(k);
+    }
+    if (mode == LBM_BATCH_PER_LATTICE) {
+        for (int prec = 0; prec < 2; ++prec)
+            for (size_t m = 0; m < idx[prec].size(); ++m) {
+                lbm_sc* h = b->members[idx[prec][m]].h;
+                lbm_batch* keep = h->batch;
+                const int rc = sc_enqueue_steps(h, ks[prec][m], b->stream);
+                h->batch = keep;
+                if (rc) {
+                    b->err = rc;
+                    return rc;
+                }
+                // sc_enqueue_steps already advanced parity and step count
+                b->members[idx[prec][m]].remaining -= ks[prec][m];
+            }
+        return LBM_OK;
+    }
+    for (int prec = 0; prec < 2; ++prec) {
+        if (idx[prec].empty()) continue;
+        const int K = *std::max_element(ks[prec].begin(), ks[prec].end());
+        const int rc = run_group(b, prec, idx[prec], ks[prec], K, mode);
+        if (rc) return rc;
+        for (size_t m = 0; m < idx[prec].size(); ++m) {
+            Member& mm = b->members[idx[prec][m]];
+            mm.h->cur ^= (ks[prec][m] & 1);
+            mm.h->steps += ks[prec][m];
+            mm.remaining -= ks[prec][m];
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_poll(lbm_batch* b, lbm_sc** done, int max_done, int* n_done) {
+    if (!b || !n_done || max_done < 0 || (max_done > 0 && !done)) return LBM_EINVAL;
+    *n_done = 0;
+    if (b->err) return b->err;
+    (void)hipSetDevice(b->device);
+    BCALL(b, hipStreamSynchronize(b->stream));
+    for (int prec = 0; prec < 2; ++prec) {
+        Group& g = b->grp[prec];
+        if (g.d_sync && g.g_mode == LBM_BATCH_PERSISTENT) {
+            unsigned flag = 0;
+            BCALL(b, hipMemcpy(&flag, g.d_sync + SYNC_TIMEOUT, sizeof(unsigned),
+                               hipMemcpyDeviceToHost));
+            if (flag) {
+                b->err = LBM_ETIMEOUT;
+                return LBM_ETIMEOUT;
+            }
+        }
+    }
+    for (const Member& m : b->members)
+        if (m.remaining <= 0 && *n_done < max_done) done[(*n_done)++] = m.h;
+    return LBM_OK;
+}
+
+int lbm_batch_stats(const lbm_batch* b, int* members, size_t* bytes_used,
+                    double* pending_site_updates) {
+    if (!b) return LBM_EINVAL;
+    if (members) *members = (int)b->members.size();
+    if (bytes_used) *bytes_used = b->used;
+    if (pending_site_updates) {
+        double s = 0.0;
+        for (const Member& m : b->members) s += (double)m.h->N * (double)std::max(0LL, m.remaining);
+        *pending_site_updates = s;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_set_tiles(lbm_batch* b, int tx9, int tx19, int ty19, int mb9, int mb19) {
+    if (!b) return LBM_EINVAL;
+    const int nt = tx9 > 0 ? tx9 : b->nt;
+    const int x19 = tx19 > 0 ? tx19 : b->tx19;
+    const int y19 = ty19 > 0 ? ty19 : b->ty19;
+    if (!cfg_supported(nt, x19, y19)) return LBM_EINVAL;
+    if (mb9 < 0 || mb19 < 0) return LBM_EINVAL;
+    b->nt = nt;
+    b->tx19 = x19;
+    b->ty19 = y19;
+    b->mb9 = mb9;
+    b->mb19 = mb19;
+    for (Group& g : b->grp) {
+        if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+        g.gexec = nullptr;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch* b) {
+    if (!b) return LBM_OK;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    for (Member& m : b->members) m.h->batch = nullptr;
+    for (Group& g : b->grp) free_group(g);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return LBM_OK;
+}
+
+}  // extern "C"

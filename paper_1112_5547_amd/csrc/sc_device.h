@@ -1,0 +1,500 @@
+// sc_device.h -- device code of the two-component Shan-Chen BGK step for
+// gfx950: velocity sets, precision policies and the fused tile-march step
+// shared by the single-lattice, batched and persistent launches.
+//
+// Method (Scarbolo et al., Sec. 2.1, eq:be, moment definitions, eq. FORCE):
+//   rho_s = sum_i f_is,  j_s = sum_i f_is c_i
+//   a_s   = -G sum_i w_i rho_s'(x + c_i) c_i       (F_s = rho_s a_s, psi = rho)
+//   u'    = (j_A/tau_A + j_B/tau_B) / (rho_A/tau_A + rho_B/tau_B)
+//   v_s   = u' + tau_s a_s                          (= u' + tau_s F_s / rho_s)
+//   f*_is = f_is + (f^eq_is(rho_s, v_s) - f_is) / tau_s
+//   f_is(x + c_i, t + 1) = f*_is(x, t)              (periodic)
+//
+// Memory layout.  Populations are SoA, one contiguous array per (species,
+// velocity): buf[(s*Q + i)*N + site], site = (z*ny + y)*nx + x.  Two buffers
+// ping-pong.  A buffer holds post-collision values f*(x, t-1) at x, so the
+// state f(x, t) is read "pulled": f_is(x, t) = buf[s][i][x - c_i].  Every
+// store is aligned and coalesced; a pulled load is misaligned by at most one
+// element along x.
+//
+// Fused step.  A block owns a transverse tile (TX x TY sites of the xy plane
+// on D3Q19, TX sites of an x row on D2Q9) and marches along the slowest axis
+// (z on D3Q19, y on D2Q9) over mb planes.  For plane m+1 it pulls the
+// populations of its own sites into registers and of a one-site ring around
+// the tile, reduces them to densities and keeps the densities of planes m-1,
+// m, m+1 (plus one spare) in a 4-slot LDS ring.  Plane m is then collided
+// from registers with the force gathered from LDS and stored.  HBM sees each
+// population read once and written once per step, plus the ring and the two
+// extra planes at chunk ends (served mostly by L2 / MALL).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sc {
+
+// ---------------------------------------------------------------------------
+// Velocity sets (export order of the C ABI).
+// ---------------------------------------------------------------------------
+template <int Q>
+struct VSet;
+
+template <>
+struct VSet<9> {
+    static constexpr int D = 2;
+    __host__ __device__ static constexpr int cx(int i) {
+        constexpr int a[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+        return a[i];
+    }
+    __host__ __device__ static constexpr int cy(int i) {
+        constexpr int a[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        return a[i];
+    }
+    __host__ __device__ static constexpr int cz(int) { return 0; }
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+};
+
+template <>
+struct VSet<19> {
+    static constexpr int D = 3;
+    __host__ __device__ static constexpr int cx(int i) {
+        constexpr int a[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0};
+        return a[i];
+    }
+    __host__ __device__ static constexpr int cy(int i) {
+        constexpr int a[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 1, -1};
+        return a[i];
+    }
+    __host__ __device__ static constexpr int cz(int i) {
+        constexpr int a[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 1, -1, 1};
+        return a[i];
+    }
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+};
+
+// Plane geometry: the march axis is the slowest lattice axis.  A velocity
+// moves (dx, dy) inside the plane and dm across planes.
+template <int Q>
+struct Geo {
+    static constexpr bool is3d = (Q == 19);
+    static constexpr int HY = is3d ? 1 : 0;  // ring rows above/below the tile
+    __host__ __device__ static constexpr int dx(int i) { return VSet<Q>::cx(i); }
+    __host__ __device__ static constexpr int dy(int i) { return is3d ? VSet<Q>::cy(i) : 0; }
+    __host__ __device__ static constexpr int dm(int i) {
+        return is3d ? VSet<Q>::cz(i) : VSet<Q>::cy(i);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Precision policies.  T: stored type; A: arithmetic type of the collision.
+// Shifted storage holds h = f - w_i rho_ref; the density then splits into
+// rho_ref + delta with delta = sum_i h (exact cancellation of the large part).
+// ---------------------------------------------------------------------------
+struct PF64 {
+    using T = double;
+    using A = double;
+    static constexpr bool shifted = false;
+    static constexpr int code = 0;
+};
+struct PF32S {
+    using T = float;
+    using A = float;
+    static constexpr bool shifted = true;
+    static constexpr int code = 1;
+};
+
+// Everything a step of one lattice needs; passed by value into kernels or
+// read from a descriptor table by batched launches.
+struct StepParams {
+    const void* src;
+    void* dst;
+    int NX, NY, NM;     // transverse extents and march extent
+    uint32_t P;         // plane size NX * NY
+    uint32_t N;         // sites
+    int ntx, nty;       // tiles across the plane
+    int nchunks, mb;    // march chunks of mb planes
+    int ny_lat;         // lattice y extent (Kolmogorov forcing period)
+    double tau[2], omega[2];
+    double G;
+    double rho_ref[2];
+    double body_A;
+};
+
+// Broadcast of block-uniform values into scalar registers.  Batched launches
+// read their StepParams from a descriptor table through a per-block index;
+// these make the compiler treat the fields as the uniform values they are
+// (scalar bases for buffer resources instead of per-lane waterfalls).
+__device__ __forceinline__ uint32_t uni32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    return ((uint64_t)uni32((uint32_t)(x >> 32)) << 32) | uni32((uint32_t)x);
+}
+__device__ __forceinline__ double unid(double x) {
+    return __builtin_bit_cast(double, uni64(__builtin_bit_cast(uint64_t, x)));
+}
+template <typename P>
+__device__ __forceinline__ P* unip(P* x) {
+    return reinterpret_cast<P*>(uni64(reinterpret_cast<uint64_t>(x)));
+}
+
+__device__ __forceinline__ int wrapi(int a, int n) {
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_nt(T* p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+
+// A scalar the optimiser may neither hoist nor fold: the per-(s, i) array
+// bases derived from it are recomputed where used (a few scalar ops) instead
+// of being hoisted out of the plane loop, where 38 of them would overflow the
+// SGPR file into VGPRs.
+__device__ __forceinline__ uint32_t opaque_sgpr(uint32_t x) {
+    asm volatile("; sc opaque %0" : "+s"(x));
+    return x;
+}
+
+// Raw buffer access.  A resource covers one (species, velocity) array
+// (< 4 GiB since N * sizeof(T) < 2^32); soff is a uniform byte offset (the
+// plane), voff the lane's byte offset.  Accesses beyond the array read 0 and
+// drop stores instead of faulting.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kBufWord3 = 0x00020000;  // gfx9-family raw buffer, 32-bit data format
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             kBufWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_load(rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// nontemporal store (aux bit 1: streaming, do not keep in L2)
+template <typename T>
+__device__ __forceinline__ void buf_store_nt(T v, rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ void buf_store_nt<double>(double v, rsrc_t r, uint32_t voff,
+                                                     uint32_t soff) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 2);
+}
+template <>
+__device__ __forceinline__ void buf_store_nt<float>(float v, rsrc_t r, uint32_t voff,
+                                                    uint32_t soff) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0u, 0u, 0));
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, v), r, voff, soff, 2);
+}
+
+// Maps a launch-order block id to a work id so that the blocks the hardware
+// places on one XCD (ids congruent mod 8) get a contiguous range of tiles:
+// neighbouring tiles then share that XCD's L2 for their ring loads.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+    if ((nblk & 7) != 0) return bid;
+    return (bid & 7) * (nblk >> 3) + (bid >> 3);
+}
+
+__device__ __forceinline__ StepParams uniform_params(const StepParams& q) {
+    StepParams p;
+    p.src = unip(q.src);
+    p.dst = unip(q.dst);
+    p.NX = (int)uni32((uint32_t)q.NX);
+    p.NY = (int)uni32((uint32_t)q.NY);
+    p.NM = (int)uni32((uint32_t)q.NM);
+    p.P = uni32(q.P);
+    p.N = uni32(q.N);
+    p.ntx = (int)uni32((uint32_t)q.ntx);
+    p.nty = (int)uni32((uint32_t)q.nty);
+    p.nchunks = (int)uni32((uint32_t)q.nchunks);
+    p.mb = (int)uni32((uint32_t)q.mb);
+    p.ny_lat = (int)uni32((uint32_t)q.ny_lat);
+    for (int s = 0; s < 2; ++s) {
+        p.tau[s] = unid(q.tau[s]);
+        p.omega[s] = unid(q.omega[s]);
+        p.rho_ref[s] = unid(q.rho_ref[s]);
+    }
+    p.G = unid(q.G);
+    p.body_A = unid(q.body_A);
+    return p;
+}
+
+// Kolmogorov body acceleration A sin(2 pi y / L_y) of Sec. 4.2 at lattice row y.
+__device__ __forceinline__ double kolmogorov(const StepParams& p, int y) {
+    return p.body_A * sin(2.0 * M_PI * (double)y / (double)p.ny_lat);
+}
+
+// Collision of one site and store of its 2Q post-collision populations.
+//   f      : the site's pulled populations f_is(x, t) (shifted h_is in FP32 mode)
+//   g[s]   : sum_i w_i rho_s(x + c_i) c_i, the gather of species s
+//   body   : external acceleration along x (0 without forcing)
+// Stores f*_is at byte offset soff + voff of the (s, i) arrays of dst.  Every
+// launch form (fused, two-pass, batched, persistent) calls this function, so
+// the per-site arithmetic is identical across them.
+template <int Q, class PR>
+__device__ __forceinline__ void collide_store(const typename PR::T (&f)[2][Q],
+                                              const typename PR::A (&g)[2][3],
+                                              const StepParams& p, double body,
+                                              char* __restrict__ dst, uint32_t pbytes,
+                                              uint32_t voff, uint32_t soff) {
+    using T = typename PR::T;
+    using A = typename PR::A;
+    pbytes = opaque_sgpr(pbytes);
+    const A om[2] = {A(p.omega[0]), A(p.omega[1])};
+    const A tau[2] = {A(p.tau[0]), A(p.tau[1])};
+    const A G = A(p.G);
+    A rho[2], rfull[2], j[2][3];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        A r = A(0), jx = A(0), jy = A(0), jz = A(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const A fv = A(f[s][i]);
+            r += fv;
+            if (VSet<Q>::cx(i)) jx += VSet<Q>::cx(i) > 0 ? fv : -fv;
+            if (VSet<Q>::cy(i)) jy += VSet<Q>::cy(i) > 0 ? fv : -fv;
+            if (VSet<Q>::cz(i)) jz += VSet<Q>::cz(i) > 0 ? fv : -fv;
+        }
+        rho[s] = r;
+        rfull[s] = PR::shifted ? A(p.rho_ref[s]) + r : r;
+        j[s][0] = jx;
+        j[s][1] = jy;
+        j[s][2] = jz;
+    }
+    // common velocity weighted by 1/tau_s, then the force shift of each species
+    const A den = rfull[0] * om[0] + rfull[1] * om[1];
+    A u[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = (j[0][a] * om[0] + j[1][a] * om[1]) / den;
+    const A bx = A(body);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int so = 1 - s;
+        A v[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[a] = u[a] + tau[s] * (-G * g[so][a]);
+        v[0] += tau[s] * bx;
+        const A vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        const A base = A(1) - A(1.5) * vv;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            A cu = A(0);
+            if (VSet<Q>::cx(i)) cu += VSet<Q>::cx(i) > 0 ? v[0] : -v[0];
+            if (VSet<Q>::cy(i)) cu += VSet<Q>::cy(i) > 0 ? v[1] : -v[1];
+            if (VSet<Q>::cz(i)) cu += VSet<Q>::cz(i) > 0 ? v[2] : -v[2];
+            const A wi = A(VSet<Q>::w(i));
+            A feq;
+            if (PR::shifted) {
+                // h^eq = f^eq - w rho_ref = w [delta + rho (3cu + 4.5cu^2 - 1.5vv)]
+                const A poly = A(3) * cu + A(4.5) * cu * cu - A(1.5) * vv;
+                feq = wi * (rho[s] + rfull[s] * poly);
+            } else {
+                feq = wi * rfull[s] * (base + A(3) * cu + A(4.5) * cu * cu);
+            }
+            const A fv = A(f[s][i]);
+            const A fo = fv + om[s] * (feq - fv);
+            buf_store_nt<T>(T(fo), make_rsrc(dst + (size_t)(s * Q + i) * pbytes, pbytes), voff,
+                            soff);
+        }
+    }
+}
+
+template <int Q, class PR, int TX, int TY>
+struct TileStep {
+    using T = typename PR::T;
+    using A = typename PR::A;
+    static constexpr int HY = Geo<Q>::HY;
+    static constexpr int FW = TX + 2;
+    static constexpr int FH = TY + 2 * HY;
+    static constexpr int NT = TX * TY;
+    static constexpr int R = HY ? 2 * FW + 2 * TY : 2;  // ring sites
+    static constexpr int SLOT = 2 * FH * FW;             // LDS elements per plane
+    static constexpr int LDS_ELEMS = 4 * SLOT;
+    static_assert(Q == 19 || TY == 1, "D2Q9 tiles are one row");
+    static_assert(R <= NT, "ring must fit in one pass of the block");
+
+    __device__ static __forceinline__ int lidx(int slot, int s, int fy, int fx) {
+        return ((slot * 2 + s) * FH + fy) * FW + fx;
+    }
+
+    // Pull the 2Q populations of one site of plane m into v and return the
+    // two species' density sums (delta densities when shifted).  pb holds the
+    // byte offsets of planes m-1, m, m+1 (uniform across the block) and off
+    // the lane's nine in-plane byte offsets (N * sizeof(T) < 2^32), so every
+    // load is a scalar base plus one precomputed 32-bit lane offset.
+    __device__ static __forceinline__ void pull(const char* __restrict__ src, uint32_t plane_bytes,
+                                                const uint32_t (&pb)[3],
+                                                const uint32_t (&off)[2 * HY + 1][3],
+                                                T (&v)[2][Q], A& d0, A& d1) {
+        plane_bytes = opaque_sgpr(plane_bytes);
+        A acc[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            acc[s] = A(0);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const rsrc_t r = make_rsrc(src + (size_t)(s * Q + i) * plane_bytes, plane_bytes);
+                const T val = buf_load<T>(r, off[HY - Geo<Q>::dy(i)][1 - Geo<Q>::dx(i)],
+                                          pb[1 - Geo<Q>::dm(i)]);
+                v[s][i] = val;
+                acc[s] += A(val);
+            }
+        }
+        d0 = acc[0];
+        d1 = acc[1];
+    }
+
+    // One tile column: march planes [m0, m1) of tile (tile_x, tile_y).
+    __device__ static __forceinline__ void run(const StepParams& p_in, int tile_x_in, int tile_y_in, int chunk_in,
+                               A* __restrict__ lds) {
+        const StepParams p = uniform_params(p_in);
+        const int tile_x = (int)uni32((uint32_t)tile_x_in);
+        const int tile_y = (int)uni32((uint32_t)tile_y_in);
+        const int chunk = (int)uni32((uint32_t)chunk_in);
+        const char* __restrict__ src = static_cast<const char*>(p.src);
+        char* __restrict__ dst = static_cast<char*>(p.dst);
+        const uint32_t pbytes = p.N * (uint32_t)sizeof(T);  // bytes of one (s, i) array
+        const int tid = threadIdx.x;
+        const int tx = tid % TX, ty = tid / TX;
+        const int X0 = tile_x * TX, Y0 = tile_y * TY;
+        const int m0 = chunk * p.mb;
+        const int m1 = min(m0 + p.mb, p.NM);
+        const int NX = p.NX, NY = p.NY, NM = p.NM;
+        const uint32_t P = p.P;
+
+        // interior site: frame position (tx, ty) -> periodic lattice position
+        const int gx = wrapi(X0 + tx, NX);
+        const int gy = HY ? wrapi(Y0 + ty, NY) : 0;
+        const bool valid = (X0 + tx < NX) && (!HY || Y0 + ty < NY);
+        uint32_t off[2 * HY + 1][3];
+#pragma unroll
+        for (int a = 0; a < 2 * HY + 1; ++a) {
+            const int yy = HY ? wrapi(gy + a - HY, NY) : 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                off[a][b] = (uint32_t)(yy * NX + wrapi(gx + b - 1, NX)) * (uint32_t)sizeof(T);
+        }
+        // ring site handled by this thread (tid < R)
+        const bool ring = tid < R;
+        int rlx = 0, rly = 0;
+        if (HY) {
+            if (tid < FW) {
+                rlx = tid - 1;
+                rly = -1;
+            } else if (tid < 2 * FW) {
+                rlx = tid - FW - 1;
+                rly = TY;
+            } else if (tid < 2 * FW + TY) {
+                rlx = -1;
+                rly = tid - 2 * FW;
+            } else {
+                rlx = TX;
+                rly = tid - 2 * FW - TY;
+            }
+        } else {
+            rlx = (tid == 0) ? -1 : TX;
+        }
+        uint32_t roff[2 * HY + 1][3];
+        {
+            const int rgx = wrapi(X0 + rlx, NX);
+            const int rgy = HY ? wrapi(Y0 + rly, NY) : 0;
+#pragma unroll
+            for (int a = 0; a < 2 * HY + 1; ++a) {
+                const int yy = HY ? wrapi(rgy + a - HY, NY) : 0;
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    roff[a][b] = (uint32_t)(yy * NX + wrapi(rgx + b - 1, NX)) * (uint32_t)sizeof(T);
+            }
+        }
+        const int own_fx = tx + 1, own_fy = ty + HY;
+        const uint32_t own_voff = (uint32_t)(gy * NX + gx) * (uint32_t)sizeof(T);
+        const int ring_fx = rlx + 1, ring_fy = rly + HY;
+
+        T cur[2][Q], nxt[2][Q];
+        A dA, dB;
+        uint32_t pb[3];
+
+        auto plane_bases = [&](int m) {
+            const int mm = wrapi(m, NM);
+            const uint32_t PB = P * (uint32_t)sizeof(T);
+            pb[0] = __builtin_amdgcn_readfirstlane((uint32_t)(mm == 0 ? NM - 1 : mm - 1) * PB);
+            pb[1] = __builtin_amdgcn_readfirstlane((uint32_t)mm * PB);
+            pb[2] = __builtin_amdgcn_readfirstlane((uint32_t)(mm == NM - 1 ? 0 : mm + 1) * PB);
+        };
+        // densities of the ring and of the interior of plane m into LDS slot
+        auto fill_plane = [&](int m, int slot) {
+            plane_bases(m);
+            if (ring) {
+                T dummy[2][Q];
+                A rA, rB;
+                pull(src, pbytes, pb, roff, dummy, rA, rB);
+                lds[lidx(slot, 0, ring_fy, ring_fx)] = rA;
+                lds[lidx(slot, 1, ring_fy, ring_fx)] = rB;
+            }
+            // keep the ring's loads from overlapping the plane kept in
+            // registers: bounds the live registers to two planes
+            __builtin_amdgcn_sched_barrier(0);
+            pull(src, pbytes, pb, off, nxt, dA, dB);
+            lds[lidx(slot, 0, own_fy, own_fx)] = dA;
+            lds[lidx(slot, 1, own_fy, own_fx)] = dB;
+        };
+
+        // prologue: planes m0-1 (densities only) and m0 (kept in registers)
+        fill_plane(m0 - 1, 0);
+        fill_plane(m0, 1);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
+
+        for (int m = m0; m < m1; ++m) {
+            const int k = m - m0;
+            fill_plane(m + 1, (k + 2) & 3);
+            __syncthreads();
+            if (valid) {
+                // force gather from the LDS density planes m-1, m, m+1
+                A g[2][3];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    A gx_ = A(0), gy_ = A(0), gz_ = A(0);
+#pragma unroll
+                    for (int i = 1; i < Q; ++i) {
+                        const int slot = (k + 1 + Geo<Q>::dm(i)) & 3;
+                        const A r = lds[lidx(slot, s, own_fy + Geo<Q>::dy(i),
+                                              own_fx + Geo<Q>::dx(i))];
+                        const A wr = A(VSet<Q>::w(i)) * r;
+                        if (VSet<Q>::cx(i)) gx_ += VSet<Q>::cx(i) > 0 ? wr : -wr;
+                        if (VSet<Q>::cy(i)) gy_ += VSet<Q>::cy(i) > 0 ? wr : -wr;
+                        if (VSet<Q>::cz(i)) gz_ += VSet<Q>::cz(i) > 0 ? wr : -wr;
+                    }
+                    g[s][0] = gx_;
+                    g[s][1] = gy_;
+                    g[s][2] = gz_;
+                }
+                const double body = p.body_A != 0.0 ? kolmogorov(p, HY ? gy : m) : 0.0;
+                collide_store<Q, PR>(cur, g, p, body, dst, pbytes, own_voff,
+                                     __builtin_amdgcn_readfirstlane((uint32_t)m * P *
+                                                                    (uint32_t)sizeof(T)));
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
+        }
+    }
+};
+
+}  // namespace sc

@@ -1,0 +1,52 @@
+// sc_internal.h -- host-side interface between the runtime / batch engine and
+// the kernel translation units of the Shan-Chen library (not exported).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "sc_device.h"
+
+namespace sc {
+
+// Number of FP64 totals accumulated by the observables reduction.
+enum {
+    T_MASS_A, T_MASS_B, T_MOM_X, T_MOM_Y, T_MOM_Z, T_MAX_U, T_KE, T_P_IN, T_N_IN, T_P_OUT,
+    T_N_OUT, T_RA_IN, T_RA_OUT, T_N_PHI_POS, T_N_NONFINITE, T_PAD, T_COUNT
+};
+constexpr int OBS_BLOCK = 256;
+
+struct ObsArgs {
+    const void* f;         // current population buffer (pulled read)
+    const double* rho;     // FP64 densities [2][N] (written by the density pass)
+    double* u;             // u_phys [3][N] or null
+    double* partial;       // [nblocks][T_COUNT]
+    int nx, ny, nz;
+    uint32_t N;
+    double G, body_A;
+    double rho_ref[2];
+    int has_probe;
+    double probe[4];       // cx, cy, cz, R
+    double r_in, r_out;    // radius of the inner ball / of the outer boundary
+};
+
+// tile tables (shared by runtime and batch engine)
+int tile_count(int Q);
+bool tile_get(int Q, int k, int* tx, int* ty);
+bool tile_supported(int Q, int tx, int ty);
+
+// single-lattice launches
+hipError_t launch_fused(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s);
+hipError_t launch_twopass(int Q, int prec, const StepParams& p, void* psi, hipStream_t s);
+hipError_t launch_init(int Q, int prec, void* f, const double* rho, const double* u, int nx,
+                       int ny, int nz, const double* rho_ref, hipStream_t s);
+hipError_t launch_get_plane(int Q, int prec, const void* f, double* out, int s_, int i, int nx,
+                            int ny, int nz, const double* rho_ref, hipStream_t s);
+hipError_t launch_set_plane(int Q, int prec, void* f, const double* in, int s_, int i, int nx,
+                            int ny, int nz, const double* rho_ref, hipStream_t s);
+hipError_t launch_observe(int Q, int prec, const ObsArgs& a, double* totals, hipStream_t s);
+int observe_blocks(uint32_t N);
+hipError_t launch_copy(void* dst, const void* src, size_t nbytes, hipStream_t s);
+
+}  // namespace sc

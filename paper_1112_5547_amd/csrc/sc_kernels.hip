@@ -1,0 +1,538 @@
+// sc_kernels.hip -- gfx950 kernels of the two-component Shan-Chen step and
+// their host launchers: fused tile-march step, two-pass step, initial
+// equilibrium, population export/import, FP64 observables with fixed-order
+// reductions, and a streaming-copy bandwidth probe.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "sc_internal.h"
+
+namespace sc {
+
+// ---------------------------------------------------------------------------
+// Tile tables.  D2Q9 tiles are one x row (ty = 1); D3Q19 tiles are TX x TY.
+// ---------------------------------------------------------------------------
+struct TileShape {
+    int tx, ty;
+};
+static const TileShape kTiles9[] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}};
+static const TileShape kTiles19[] = {{32, 4}, {64, 4}, {32, 8}, {64, 8}, {16, 16}, {32, 16}};
+
+int tile_count(int Q) {
+    return Q == 9 ? (int)(sizeof(kTiles9) / sizeof(kTiles9[0]))
+                  : (Q == 19 ? (int)(sizeof(kTiles19) / sizeof(kTiles19[0])) : 0);
+}
+
+bool tile_get(int Q, int k, int* tx, int* ty) {
+    if (k < 0 || k >= tile_count(Q)) return false;
+    const TileShape t = Q == 9 ? kTiles9[k] : kTiles19[k];
+    *tx = t.tx;
+    *ty = t.ty;
+    return true;
+}
+
+bool tile_supported(int Q, int tx, int ty) {
+    for (int k = 0; k < tile_count(Q); ++k) {
+        int a, b;
+        tile_get(Q, k, &a, &b);
+        if (a == tx && b == ty) return true;
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Fused step: one block per (tile, march chunk).
+// ---------------------------------------------------------------------------
+// Minimum waves per SIMD the register allocator must allow for the fused
+// step: two planes of populations stay in registers without scratch at
+// 2 waves (D3Q19 FP64, 218 VGPRs), 3 (D2Q9 FP64, D3Q19 FP32) and 4 (D2Q9 FP32).
+template <int Q, class PR>
+struct FusedWaves {
+    static constexpr int value = PR::shifted ? (Q == 19 ? 3 : 4) : (Q == 19 ? 2 : 3);
+};
+
+template <int Q, class PR, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+    __attribute__((amdgpu_waves_per_eu(FusedWaves<Q, PR>::value))) k_step_fused(StepParams p) {
+    using TS = TileStep<Q, PR, TX, TY>;
+    __shared__ typename PR::A lds[TS::LDS_ELEMS];
+    const int w = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int tiles = p.ntx * p.nty;
+    const int chunk = w / tiles;
+    const int t = w - chunk * tiles;
+    TS::run(p, t % p.ntx, t / p.ntx, chunk, lds);
+}
+
+template <int Q, class PR, int TX, int TY>
+static hipError_t launch_fused_t(const StepParams& p, hipStream_t s) {
+    const unsigned nblk = (unsigned)p.ntx * p.nty * p.nchunks;
+    hipLaunchKernelGGL((k_step_fused<Q, PR, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, p);
+    return hipGetLastError();
+}
+
+template <class PR>
+static hipError_t launch_fused_p(int Q, int tx, int ty, const StepParams& p, hipStream_t s) {
+    if (Q == 9) {
+        switch (tx) {
+            case 64: return launch_fused_t<9, PR, 64, 1>(p, s);
+            case 128: return launch_fused_t<9, PR, 128, 1>(p, s);
+            case 256: return launch_fused_t<9, PR, 256, 1>(p, s);
+            case 512: return launch_fused_t<9, PR, 512, 1>(p, s);
+        }
+    } else {
+        const int key = tx * 1000 + ty;
+        switch (key) {
+            case 32004: return launch_fused_t<19, PR, 32, 4>(p, s);
+            case 64004: return launch_fused_t<19, PR, 64, 4>(p, s);
+            case 32008: return launch_fused_t<19, PR, 32, 8>(p, s);
+            case 64008: return launch_fused_t<19, PR, 64, 8>(p, s);
+            case 16016: return launch_fused_t<19, PR, 16, 16>(p, s);
+            case 32016: return launch_fused_t<19, PR, 32, 16>(p, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s) {
+    return prec == 0 ? launch_fused_p<PF64>(Q, tx, ty, p, s)
+                     : launch_fused_p<PF32S>(Q, tx, ty, p, s);
+}
+
+// ---------------------------------------------------------------------------
+// Site helpers for the simple (one thread per site) kernels.
+// ---------------------------------------------------------------------------
+struct SiteGeom {
+    int x, y, z;
+};
+
+__device__ __forceinline__ SiteGeom site_xyz(uint32_t site, int nx, int ny) {
+    SiteGeom g;
+    g.x = (int)(site % (uint32_t)nx);
+    const uint32_t r = site / (uint32_t)nx;
+    g.y = (int)(r % (uint32_t)ny);
+    g.z = (int)(r / (uint32_t)ny);
+    return g;
+}
+
+__device__ __forceinline__ uint32_t site_at(const SiteGeom& g, int dx, int dy, int dz, int nx,
+                                            int ny, int nz) {
+    const int x = wrapi(g.x + dx, nx), y = wrapi(g.y + dy, ny), z = wrapi(g.z + dz, nz);
+    return ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)nx + (uint32_t)x;
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass step: densities to an HBM psi array, then collide with a global
+// gather.  Moves (6Q + 4) values per site instead of 4Q; kept as the plain
+// form the fused kernel is measured against.
+// ---------------------------------------------------------------------------
+template <int Q, class PR>
+__global__ void __launch_bounds__(256) k_density(StepParams p, typename PR::A* psi, int nx, int ny,
+                                                 int nz) {
+    using T = typename PR::T;
+    using A = typename PR::A;
+    const uint32_t site = blockIdx.x * 256u + threadIdx.x;
+    if (site >= p.N) return;
+    const T* f = static_cast<const T*>(p.src);
+    const SiteGeom g = site_xyz(site, nx, ny);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        A r = A(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            r += A(f[(size_t)(s * Q + i) * p.N +
+                     site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)]);
+        psi[(size_t)s * p.N + site] = r;
+    }
+}
+
+template <int Q, class PR>
+__global__ void __launch_bounds__(256) k_collide2(StepParams p, const typename PR::A* psi, int nx,
+                                                  int ny, int nz) {
+    using T = typename PR::T;
+    using A = typename PR::A;
+    const uint32_t site = blockIdx.x * 256u + threadIdx.x;
+    if (site >= p.N) return;
+    const T* f = static_cast<const T*>(p.src);
+    const SiteGeom g = site_xyz(site, nx, ny);
+    T v[2][Q];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            v[s][i] = f[(size_t)(s * Q + i) * p.N +
+                        site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)];
+    A gs[2][3];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        A gx = A(0), gy = A(0), gz = A(0);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const A r = psi[(size_t)s * p.N +
+                            site_at(g, VSet<Q>::cx(i), VSet<Q>::cy(i), VSet<Q>::cz(i), nx, ny, nz)];
+            const A wr = A(VSet<Q>::w(i)) * r;
+            if (VSet<Q>::cx(i)) gx += VSet<Q>::cx(i) > 0 ? wr : -wr;
+            if (VSet<Q>::cy(i)) gy += VSet<Q>::cy(i) > 0 ? wr : -wr;
+            if (VSet<Q>::cz(i)) gz += VSet<Q>::cz(i) > 0 ? wr : -wr;
+        }
+        gs[s][0] = gx;
+        gs[s][1] = gy;
+        gs[s][2] = gz;
+    }
+    const double body = p.body_A != 0.0 ? kolmogorov(p, g.y) : 0.0;
+    collide_store<Q, PR>(v, gs, p, body, static_cast<char*>(p.dst), p.N * (uint32_t)sizeof(T),
+                         site * (uint32_t)sizeof(T), 0u);
+}
+
+template <int Q, class PR>
+static hipError_t launch_twopass_t(const StepParams& p, void* psi, hipStream_t s) {
+    using A = typename PR::A;
+    const unsigned nblk = (p.N + 255u) / 256u;
+    int nx, ny, nz;
+    if (Q == 19) {
+        nx = p.NX;
+        ny = p.NY;
+        nz = p.NM;
+    } else {
+        nx = p.NX;
+        ny = p.NM;
+        nz = 1;
+    }
+    hipLaunchKernelGGL((k_density<Q, PR>), dim3(nblk), dim3(256), 0, s, p, static_cast<A*>(psi),
+                       nx, ny, nz);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_collide2<Q, PR>), dim3(nblk), dim3(256), 0, s, p,
+                       static_cast<const A*>(psi), nx, ny, nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_twopass(int Q, int prec, const StepParams& p, void* psi, hipStream_t s) {
+    if (Q == 9)
+        return prec == 0 ? launch_twopass_t<9, PF64>(p, psi, s) : launch_twopass_t<9, PF32S>(p, psi, s);
+    return prec == 0 ? launch_twopass_t<19, PF64>(p, psi, s) : launch_twopass_t<19, PF32S>(p, psi, s);
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: buf_is(y) = f_is^eq(rho_s(y + c_i), u(y + c_i)), so that the
+// pulled read at x gives f_is(x, 0) = f^eq(rho_s(x), u(x)).
+// ---------------------------------------------------------------------------
+template <int Q, class PR>
+__global__ void __launch_bounds__(256) k_init(typename PR::T* f, const double* rho, const double* u,
+                                              int nx, int ny, int nz, uint32_t N, double rA,
+                                              double rB) {
+    using T = typename PR::T;
+    const uint32_t site = blockIdx.x * 256u + threadIdx.x;
+    if (site >= N) return;
+    const SiteGeom g = site_xyz(site, nx, ny);
+    const double rref[2] = {rA, rB};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const uint32_t x = site_at(g, VSet<Q>::cx(i), VSet<Q>::cy(i), VSet<Q>::cz(i), nx, ny, nz);
+        double ux = 0.0, uy = 0.0, uz = 0.0;
+        if (u) {
+            ux = u[x];
+            uy = u[(size_t)N + x];
+            uz = u[2 * (size_t)N + x];
+        }
+        const double cu = VSet<Q>::cx(i) * ux + VSet<Q>::cy(i) * uy + VSet<Q>::cz(i) * uz;
+        const double uu = ux * ux + uy * uy + uz * uz;
+        const double poly = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const double fe = VSet<Q>::w(i) * rho[(size_t)s * N + x] * poly;
+            const double val = PR::shifted ? fe - VSet<Q>::w(i) * rref[s] : fe;
+            f[(size_t)(s * Q + i) * N + site] = T(val);
+        }
+    }
+}
+
+hipError_t launch_init(int Q, int prec, void* f, const double* rho, const double* u, int nx,
+                       int ny, int nz, const double* rho_ref, hipStream_t s) {
+    const uint32_t N = (uint32_t)nx * ny * nz;
+    const unsigned nblk = (N + 255u) / 256u;
+#define SC_INIT(QQ, PP)                                                                      \
+    hipLaunchKernelGGL((k_init<QQ, PP>), dim3(nblk), dim3(256), 0, s,                        \
+                       static_cast<typename PP::T*>(f), rho, u, nx, ny, nz, N, rho_ref[0], \
+                       rho_ref[1])
+    if (Q == 9) {
+        if (prec == 0) SC_INIT(9, PF64); else SC_INIT(9, PF32S);
+    } else {
+        if (prec == 0) SC_INIT(19, PF64); else SC_INIT(19, PF32S);
+    }
+#undef SC_INIT
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Population export / import of one (s, i) array, converting the pulled
+// storage to the state f(x, t) (and shifted values back to full ones).
+// ---------------------------------------------------------------------------
+template <int Q, class PR>
+__global__ void __launch_bounds__(256) k_get_plane(const typename PR::T* f, double* out, int s_,
+                                                   int i, int nx, int ny, int nz, uint32_t N,
+                                                   double shift) {
+    const uint32_t site = blockIdx.x * 256u + threadIdx.x;
+    if (site >= N) return;
+    const SiteGeom g = site_xyz(site, nx, ny);
+    const uint32_t src = site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz);
+    out[site] = (double)f[(size_t)(s_ * Q + i) * N + src] + shift;
+}
+
+template <int Q, class PR>
+__global__ void __launch_bounds__(256) k_set_plane(typename PR::T* f, const double* in, int s_,
+                                                   int i, int nx, int ny, int nz, uint32_t N,
+                                                   double shift) {
+    using T = typename PR::T;
+    const uint32_t site = blockIdx.x * 256u + threadIdx.x;
+    if (site >= N) return;
+    const SiteGeom g = site_xyz(site, nx, ny);
+    const uint32_t src = site_at(g, VSet<Q>::cx(i), VSet<Q>::cy(i), VSet<Q>::cz(i), nx, ny, nz);
+    f[(size_t)(s_ * Q + i) * N + site] = T(in[src] - shift);
+}
+
+hipError_t launch_get_plane(int Q, int prec, const void* f, double* out, int s_, int i, int nx,
+                            int ny, int nz, const double* rho_ref, hipStream_t s) {
+    const uint32_t N = (uint32_t)nx * ny * nz;
+    const unsigned nblk = (N + 255u) / 256u;
+    const double wi = Q == 9 ? VSet<9>::w(i) : VSet<19>::w(i);
+    const double shift = prec == 0 ? 0.0 : wi * rho_ref[s_];
+#define SC_GET(QQ, PP)                                                                        \
+    hipLaunchKernelGGL((k_get_plane<QQ, PP>), dim3(nblk), dim3(256), 0, s,                    \
+                       static_cast<const typename PP::T*>(f), out, s_, i, nx, ny, nz, N, shift)
+    if (Q == 9) {
+        if (prec == 0) SC_GET(9, PF64); else SC_GET(9, PF32S);
+    } else {
+        if (prec == 0) SC_GET(19, PF64); else SC_GET(19, PF32S);
+    }
+#undef SC_GET
+    return hipGetLastError();
+}
+
+hipError_t launch_set_plane(int Q, int prec, void* f, const double* in, int s_, int i, int nx,
+                            int ny, int nz, const double* rho_ref, hipStream_t s) {
+    const uint32_t N = (uint32_t)nx * ny * nz;
+    const unsigned nblk = (N + 255u) / 256u;
+    const double wi = Q == 9 ? VSet<9>::w(i) : VSet<19>::w(i);
+    const double shift = prec == 0 ? 0.0 : wi * rho_ref[s_];
+#define SC_SET(QQ, PP)                                                                      \
+    hipLaunchKernelGGL((k_set_plane<QQ, PP>), dim3(nblk), dim3(256), 0, s,                  \
+                       static_cast<typename PP::T*>(f), in, s_, i, nx, ny, nz, N, shift)
+    if (Q == 9) {
+        if (prec == 0) SC_SET(9, PF64); else SC_SET(9, PF32S);
+    } else {
+        if (prec == 0) SC_SET(19, PF64); else SC_SET(19, PF32S);
+    }
+#undef SC_SET
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 observables.
+//   pass 1: rho_s(x) = sum_i f_is(x, t)      (FP64, shifted: rho_ref + sum h)
+//   pass 2: j_s, force F_s = -G rho_s sum_i w_i rho_s'(x + c_i) c_i (+ body),
+//           u_phys = (j_A + j_B + F/2) / rho, bulk pressure, probe means,
+//           phi >= 0 count, non-finite count; per-block partials reduced in a
+//           fixed LDS tree order
+//   pass 3: one block reduces the partials in a fixed order.
+// ---------------------------------------------------------------------------
+template <int Q, class PR>
+__global__ void __launch_bounds__(256) k_rho64(const typename PR::T* f, double* rho, int nx, int ny,
+                                               int nz, uint32_t N, double rA, double rB) {
+    const uint32_t site = blockIdx.x * 256u + threadIdx.x;
+    if (site >= N) return;
+    const SiteGeom g = site_xyz(site, nx, ny);
+    const double rref[2] = {rA, rB};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        double r = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            r += (double)f[(size_t)(s * Q + i) * N +
+                           site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)];
+        rho[(size_t)s * N + site] = PR::shifted ? rref[s] + r : r;
+    }
+}
+
+__device__ __forceinline__ bool is_max_slot(int k) { return k == T_MAX_U; }
+
+template <int Q, class PR>
+__global__ void __launch_bounds__(OBS_BLOCK) k_observe(ObsArgs a) {
+    using T = typename PR::T;
+    __shared__ double red[T_COUNT][OBS_BLOCK];
+    const uint32_t site = blockIdx.x * (uint32_t)OBS_BLOCK + threadIdx.x;
+    double v[T_COUNT];
+#pragma unroll
+    for (int k = 0; k < T_COUNT; ++k) v[k] = 0.0;
+    if (site < a.N) {
+        const T* f = static_cast<const T*>(a.f);
+        const uint32_t N = a.N;
+        const SiteGeom g = site_xyz(site, a.nx, a.ny);
+        double j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double fv =
+                    (double)f[(size_t)(s * Q + i) * N +
+                              site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), a.nx,
+                                      a.ny, a.nz)];
+                j[0] += VSet<Q>::cx(i) * fv;
+                j[1] += VSet<Q>::cy(i) * fv;
+                j[2] += VSet<Q>::cz(i) * fv;
+            }
+        const double rA = a.rho[site], rB = a.rho[(size_t)N + site];
+        double gs[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const uint32_t nb = site_at(g, VSet<Q>::cx(i), VSet<Q>::cy(i), VSet<Q>::cz(i), a.nx,
+                                        a.ny, a.nz);
+            const double w = VSet<Q>::w(i);
+            const double nA = a.rho[nb], nB = a.rho[(size_t)N + nb];
+            gs[0][0] += w * nA * VSet<Q>::cx(i);
+            gs[0][1] += w * nA * VSet<Q>::cy(i);
+            gs[0][2] += w * nA * VSet<Q>::cz(i);
+            gs[1][0] += w * nB * VSet<Q>::cx(i);
+            gs[1][1] += w * nB * VSet<Q>::cy(i);
+            gs[1][2] += w * nB * VSet<Q>::cz(i);
+        }
+        const double rho = rA + rB;
+        double Ft[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Ft[c] = -a.G * rA * gs[1][c] - a.G * rB * gs[0][c];
+        if (a.body_A != 0.0) Ft[0] += rho * a.body_A * sin(2.0 * M_PI * (double)g.y / (double)a.ny);
+        double u[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) u[c] = (j[c] + 0.5 * Ft[c]) / rho;
+        const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const double umag = sqrt(uu);
+        if (a.u) {
+            a.u[site] = u[0];
+            a.u[(size_t)N + site] = u[1];
+            a.u[2 * (size_t)N + site] = u[2];
+        }
+        const double cs2 = 1.0 / 3.0;
+        const double p = cs2 * rho + cs2 * a.G * rA * rB;
+        v[T_MASS_A] = rA;
+        v[T_MASS_B] = rB;
+        v[T_MOM_X] = j[0];
+        v[T_MOM_Y] = j[1];
+        v[T_MOM_Z] = j[2];
+        v[T_MAX_U] = umag;
+        v[T_KE] = uu;
+        v[T_N_PHI_POS] = (rA - rB >= 0.0) ? 1.0 : 0.0;
+        v[T_N_NONFINITE] = (isfinite(rA) && isfinite(rB) && isfinite(uu)) ? 0.0 : 1.0;
+        if (a.has_probe) {
+            double dx = g.x - a.probe[0], dy = g.y - a.probe[1], dz = g.z - a.probe[2];
+            dx -= a.nx * round(dx / a.nx);
+            dy -= a.ny * round(dy / a.ny);
+            dz = a.nz > 1 ? dz - a.nz * round(dz / a.nz) : 0.0;
+            const double d = sqrt(dx * dx + dy * dy + dz * dz);
+            if (d <= a.r_in) {
+                v[T_P_IN] = p;
+                v[T_N_IN] = 1.0;
+                v[T_RA_IN] = rA;
+            } else if (d > a.r_out) {
+                v[T_P_OUT] = p;
+                v[T_N_OUT] = 1.0;
+                v[T_RA_OUT] = rA;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < T_COUNT; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int stride = OBS_BLOCK / 2; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride) {
+#pragma unroll
+            for (int k = 0; k < T_COUNT; ++k) {
+                const double o = red[k][threadIdx.x + stride];
+                red[k][threadIdx.x] = is_max_slot(k) ? fmax(red[k][threadIdx.x], o)
+                                                     : red[k][threadIdx.x] + o;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < T_COUNT) a.partial[(size_t)blockIdx.x * T_COUNT + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) k_finalize(const double* partial, int nparts, double* out) {
+    __shared__ double red[T_COUNT][256];
+    double v[T_COUNT];
+#pragma unroll
+    for (int k = 0; k < T_COUNT; ++k) v[k] = 0.0;
+    for (int r = threadIdx.x; r < nparts; r += 256) {
+#pragma unroll
+        for (int k = 0; k < T_COUNT; ++k) {
+            const double o = partial[(size_t)r * T_COUNT + k];
+            v[k] = is_max_slot(k) ? fmax(v[k], o) : v[k] + o;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < T_COUNT; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride) {
+#pragma unroll
+            for (int k = 0; k < T_COUNT; ++k) {
+                const double o = red[k][threadIdx.x + stride];
+                red[k][threadIdx.x] = is_max_slot(k) ? fmax(red[k][threadIdx.x], o)
+                                                     : red[k][threadIdx.x] + o;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < T_COUNT) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+int observe_blocks(uint32_t N) { return (int)((N + OBS_BLOCK - 1) / OBS_BLOCK); }
+
+hipError_t launch_observe(int Q, int prec, const ObsArgs& a, double* totals, hipStream_t s) {
+    const unsigned nblk = (unsigned)observe_blocks(a.N);
+    double* rho = const_cast<double*>(a.rho);
+#define SC_OBS(QQ, PP)                                                                          \
+    do {                                                                                        \
+        hipLaunchKernelGGL((k_rho64<QQ, PP>), dim3(nblk), dim3(256), 0, s,                      \
+                           static_cast<const typename PP::T*>(a.f), rho, a.nx, a.ny, a.nz, a.N, \
+                           a.rho_ref[0], a.rho_ref[1]);                                         \
+        hipLaunchKernelGGL((k_observe<QQ, PP>), dim3(nblk), dim3(OBS_BLOCK), 0, s, a);          \
+    } while (0)
+    if (Q == 9) {
+        if (prec == 0) SC_OBS(9, PF64); else SC_OBS(9, PF32S);
+    } else {
+        if (prec == 0) SC_OBS(19, PF64); else SC_OBS(19, PF32S);
+    }
+#undef SC_OBS
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a.partial, (int)nblk, totals);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Streaming copy (8-byte elements, nontemporal stores, four loads in flight
+// per thread): the achievable read+write bandwidth for the step's pattern.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_copy(uint64_t* __restrict__ dst,
+                                              const uint64_t* __restrict__ src, size_t n) {
+    const size_t stride = (size_t)gridDim.x * 256u;
+    size_t i = (size_t)blockIdx.x * 256u + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const uint64_t a = src[i], b = src[i + stride], c = src[i + 2 * stride],
+                       d = src[i + 3 * stride];
+        store_nt(dst + i, a);
+        store_nt(dst + i + stride, b);
+        store_nt(dst + i + 2 * stride, c);
+        store_nt(dst + i + 3 * stride, d);
+    }
+    for (; i < n; i += stride) store_nt(dst + i, src[i]);
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t nbytes, hipStream_t s) {
+    const size_t n = nbytes / 8;
+    size_t blocks = (n + 4 * 256 - 1) / (4 * 256);
+    if (blocks > 65536) blocks = 65536;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<uint64_t*>(dst),
+                       static_cast<const uint64_t*>(src), n);
+    return hipGetLastError();
+}
+
+}  // namespace sc

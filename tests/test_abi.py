@@ -1,0 +1,99 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function include/lbm_sc.h declares; host-only entry points validate their
+arguments.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm_sc.h")
+LIB = os.path.join(ROOT, "paper_1112_5547_amd", "liblbm_sc.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_(?:sc|batch)_\w+)\s*\(", text)))
+
+
+def _lib():
+    if not os.path.exists(LIB):
+        from paper_1112_5547_amd import build
+        build.build()
+    from paper_1112_5547_amd import _abi
+    return _abi.lib()
+
+
+def test_header_declares_the_core_calls():
+    names = _declared()
+    for core in ("lbm_sc_create", "lbm_sc_init", "lbm_sc_step", "lbm_sc_moments",
+                 "lbm_sc_destroy", "lbm_batch_run"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(LIB if os.path.exists(LIB) else _lib()._name)
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1112_5547_amd import _abi
+    bound = {n for n, _, _ in _abi.SIGNATURES}
+    assert bound == set(_declared())
+
+
+def test_params_validation_and_sizes():
+    from paper_1112_5547_amd import _abi
+    L = _lib()
+    p = _abi.Params()
+    ok = L.lbm_sc_params_default(ctypes.byref(p), 19, 256, 256, 256, 1.0, 1.0, 1.6)
+    assert ok == 0
+    n = 256 ** 3
+    need = L.lbm_sc_bytes_needed(ctypes.byref(p))
+    assert need >= 2 * (2 * 19 * n * 8)          # two FP64 population buffers
+    assert need < 2 * (2 * 19 * n * 8) * 1.2      # plus small side arrays
+    p.precision = _abi.LBM_FP32_SHIFTED
+    need32 = L.lbm_sc_bytes_needed(ctypes.byref(p))
+    assert need32 < need
+    bad = [
+        (9, 8, 8, 2, 1.0, 1.0, 1.0),     # D2Q9 with nz > 1
+        (19, 0, 8, 8, 1.0, 1.0, 1.0),    # empty lattice
+        (9, 8, 8, 1, 0.5, 1.0, 1.0),     # tau = 1/2: zero viscosity
+        (9, 8, 8, 1, 1.0, 0.4, 1.0),
+        (9, 8, 8, 1, 1.0, 1.0, -0.1),    # attractive coupling not supported
+        (7, 8, 8, 1, 1.0, 1.0, 1.0),     # unknown lattice
+        (19, 1024, 1024, 1024, 1.0, 1.0, 1.0),  # beyond 2^29 sites
+    ]
+    for args in bad:
+        q = _abi.Params()
+        assert L.lbm_sc_params_default(ctypes.byref(q), *args) == _abi.LBM_EINVAL, args
+        assert L.lbm_sc_bytes_needed(ctypes.byref(q)) == 0
+
+
+def test_tile_tables_and_strerror():
+    L = _lib()
+    for q in (9, 19):
+        k = L.lbm_sc_tile_count(q)
+        assert k >= 4
+        for i in range(k):
+            x, y = ctypes.c_int(), ctypes.c_int()
+            assert L.lbm_sc_tile_get(q, i, ctypes.byref(x), ctypes.byref(y)) == 0
+            if q == 9:
+                assert y.value == 1
+            # one ring of halo sites must fit in a block
+            ring = 2 * (x.value + 2) + 2 * y.value if q == 19 else 2
+            assert ring <= x.value * y.value
+    assert L.lbm_sc_tile_count(5) == 0
+    for st in range(-7, 1):
+        assert L.lbm_sc_strerror(st)
+    assert L.lbm_sc_destroy(None) == 0
+
+
+def test_null_handles_are_rejected():
+    L = _lib()
+    assert L.lbm_sc_step(None, 1) == -1
+    assert L.lbm_sc_init(None, None, None, None) == -1
+    assert L.lbm_batch_run(None, 1, 0) == -1
