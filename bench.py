@@ -38,10 +38,12 @@ def b_alg(q: int, esize: int) -> int:
 
 def time_lattice(fields, precision, steps, warmup, kernel=None):
     import torch
-    from paper_1112_5547_amd import Lattice
+    from paper_1112_5547_amd import Lattice, autotune
     lat = Lattice(Q19, L, L, L, tau_A=TAU, tau_B=TAU, G=G, precision=precision)
     if kernel:
         lat.set_kernel(*kernel)
+    else:
+        autotune.apply(lat)  # tuned tile / march chunk when the table has one
     lat.init(fields.rho_A, fields.rho_B)
     T0 = lat.totals()
     lat.step(warmup)
@@ -81,6 +83,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling leg")
+    ap.add_argument("--kernel", type=str, default=None,
+                    help="variant,tx,ty,mb of the FP64 step (default: tuned table)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -95,7 +100,8 @@ def main():
     fields = sc_inputs.spinodal(L, L, L, rho0=0.5, noise=0.01, seed=3)
     n = L ** 3
 
-    r64 = time_lattice(fields, "fp64", args.steps, args.warmup)
+    kernel = tuple(int(v) for v in args.kernel.split(",")) if args.kernel else None
+    r64 = time_lattice(fields, "fp64", args.steps, args.warmup, kernel)
     mlups = n * args.steps / r64["wall_s"] / 1e6
     ach = b_alg(Q19, 8) * n / (r64["kernel_ms"] * 1e-3) / 1e9
     out = {
@@ -132,7 +138,8 @@ def main():
             "kernel": list(r32["kernel"]),
             "mass_drift_A": (r32["T"]["mass_A"] - r32["T0"]["mass_A"]) / r32["T0"]["mass_A"],
         }
-    out["copy_ceiling_GBps"] = round(copy_bench(2 << 30, reps=10), 1)
+    if not args.no_copy:
+        out["copy_ceiling_GBps"] = round(copy_bench(2 << 30, reps=10), 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(fields)
     print(json.dumps(out), flush=True)

@@ -173,7 +173,10 @@ int lbm_sc_sync(lbm_sc *h);
 int lbm_sc_time_steps(lbm_sc *h, int n, float *ms);
 
 /* Kernel configuration.  variant: 0 = fused single-kernel step (default),
- * 1 = two kernels per step (densities, then collide).  tx, ty: transverse
+ * 1 = two kernels per step (densities, then collide), 2 = fused step with a
+ * three-plane register pipeline (loads of plane m+2 overlap the collision of
+ * plane m), 3 = fused step holding no plane across iterations (plane m is
+ * pulled again, from cache, for its collision).  tx, ty: transverse
  * tile (ty = 1 on D2Q9); mb: sites marched per block along the slowest axis
  * (y on D2Q9, z on D3Q19).  Unsupported tiles return LBM_EINVAL. */
 int lbm_sc_set_kernel(lbm_sc *h, int variant, int tx, int ty, int mb);

@@ -101,9 +101,19 @@ class LbmError(RuntimeError):
 
 
 def lib():
-    """The loaded library; raises if it has not been built."""
+    """The loaded library; raises if it has not been built.
+
+    PyTorch bundles its own HIP and HSA runtimes under the same sonames as
+    /opt/rocm's.  Importing torch first lets the loader bind this library to
+    the runtime torch already mapped, so one process holds one HIP runtime
+    (two would both try to own the device).
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(
                 f"{LIB_PATH} is missing: build it with paper_1112_5547_amd.build.build() "

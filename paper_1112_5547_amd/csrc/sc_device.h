@@ -340,18 +340,23 @@ struct TileStep {
                                                 const uint32_t (&off)[2 * HY + 1][3],
                                                 T (&v)[2][Q], A& d0, A& d1) {
         plane_bytes = opaque_sgpr(plane_bytes);
+        // all 2Q loads are issued before any is consumed: the sums below must
+        // not let the scheduler serialise them through one register
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const rsrc_t r = make_rsrc(src + (size_t)(s * Q + i) * plane_bytes, plane_bytes);
+                v[s][i] = buf_load<T>(r, off[HY - Geo<Q>::dy(i)][1 - Geo<Q>::dx(i)],
+                                      pb[1 - Geo<Q>::dm(i)]);
+            }
+        __builtin_amdgcn_sched_group_barrier(0x020, 2 * Q, 0);  // 2Q VMEM reads first
         A acc[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             acc[s] = A(0);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const rsrc_t r = make_rsrc(src + (size_t)(s * Q + i) * plane_bytes, plane_bytes);
-                const T val = buf_load<T>(r, off[HY - Geo<Q>::dy(i)][1 - Geo<Q>::dx(i)],
-                                          pb[1 - Geo<Q>::dm(i)]);
-                v[s][i] = val;
-                acc[s] += A(val);
-            }
+            for (int i = 0; i < Q; ++i) acc[s] += A(v[s][i]);
         }
         d0 = acc[0];
         d1 = acc[1];
@@ -493,6 +498,368 @@ struct TileStep {
             for (int s = 0; s < 2; ++s)
 #pragma unroll
                 for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Pipelined march.  Same tile / march / LDS-ring structure as TileStep, but
+// three planes of populations live in registers: while plane m is collided,
+// the loads of plane m+2 are already in flight, so each wave overlaps its own
+// memory latency with its collision instead of waiting at the barrier.  The
+// ring densities are split into (site, species) tasks of Q loads spread over
+// all threads of the block.
+// ---------------------------------------------------------------------------
+template <int Q, class PR, int TX, int TY>
+struct TileStepPipe {
+    using T = typename PR::T;
+    using A = typename PR::A;
+    using Base = TileStep<Q, PR, TX, TY>;
+    static constexpr int HY = Geo<Q>::HY;
+    static constexpr int FW = TX + 2;
+    static constexpr int FH = TY + 2 * HY;
+    static constexpr int NT = TX * TY;
+    static constexpr int R = Base::R;
+    static constexpr int RT = 2 * R;                        // ring (site, species) tasks
+    static constexpr int RPT = (RT + NT - 1) / NT;          // ring tasks per thread
+    static constexpr int LDS_ELEMS = Base::LDS_ELEMS;
+
+    __device__ static __forceinline__ int lidx(int slot, int s, int fy, int fx) {
+        return Base::lidx(slot, s, fy, fx);
+    }
+
+    // ring site k -> frame position
+    __device__ static __forceinline__ void ring_pos(int k, int& lx, int& ly) {
+        if (HY) {
+            if (k < FW) {
+                lx = k - 1;
+                ly = -1;
+            } else if (k < 2 * FW) {
+                lx = k - FW - 1;
+                ly = TY;
+            } else if (k < 2 * FW + TY) {
+                lx = -1;
+                ly = k - 2 * FW;
+            } else {
+                lx = TX;
+                ly = k - 2 * FW - TY;
+            }
+        } else {
+            lx = k == 0 ? -1 : TX;
+            ly = 0;
+        }
+    }
+
+    // Sum of the Q pulled populations of one species at an in-plane byte
+    // offset set (one ring task).
+    __device__ static __forceinline__ A pull_species(const char* __restrict__ src,
+                                                     uint32_t plane_bytes, int s,
+                                                     const uint32_t (&pb)[3],
+                                                     const uint32_t (&off)[2 * HY + 1][3]) {
+        plane_bytes = opaque_sgpr(plane_bytes);
+        T v[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const rsrc_t r = make_rsrc(src + (size_t)(s * Q + i) * plane_bytes, plane_bytes);
+            v[i] = buf_load<T>(r, off[HY - Geo<Q>::dy(i)][1 - Geo<Q>::dx(i)],
+                               pb[1 - Geo<Q>::dm(i)]);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x020, Q, 0);  // Q VMEM reads first
+        A acc = A(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc += A(v[i]);
+        return acc;
+    }
+
+    __device__ static __forceinline__ void run(const StepParams& p_in, int tile_x_in,
+                                               int tile_y_in, int chunk_in, A* __restrict__ lds) {
+        const StepParams p = uniform_params(p_in);
+        const int tile_x = (int)uni32((uint32_t)tile_x_in);
+        const int tile_y = (int)uni32((uint32_t)tile_y_in);
+        const int chunk = (int)uni32((uint32_t)chunk_in);
+        const char* __restrict__ src = static_cast<const char*>(p.src);
+        char* __restrict__ dst = static_cast<char*>(p.dst);
+        const uint32_t pbytes = p.N * (uint32_t)sizeof(T);
+        const int tid = threadIdx.x;
+        const int tx = tid % TX, ty = tid / TX;
+        const int X0 = tile_x * TX, Y0 = tile_y * TY;
+        const int m0 = chunk * p.mb;
+        const int m1 = min(m0 + p.mb, p.NM);
+        const int NX = p.NX, NY = p.NY, NM = p.NM;
+        const uint32_t P = p.P;
+
+        const int gx = wrapi(X0 + tx, NX);
+        const int gy = HY ? wrapi(Y0 + ty, NY) : 0;
+        const bool valid = (X0 + tx < NX) && (!HY || Y0 + ty < NY);
+        uint32_t off[2 * HY + 1][3];
+#pragma unroll
+        for (int a = 0; a < 2 * HY + 1; ++a) {
+            const int yy = HY ? wrapi(gy + a - HY, NY) : 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                off[a][b] = (uint32_t)(yy * NX + wrapi(gx + b - 1, NX)) * (uint32_t)sizeof(T);
+        }
+        // ring tasks of this thread: task = tid + k*NT -> (site task/2, species task%2)
+        uint32_t roff[RPT][2 * HY + 1][3];
+        int rfx[RPT], rfy[RPT], rsp[RPT];
+        bool rok[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int task = tid + k * NT;
+            rok[k] = task < RT;
+            const int site = rok[k] ? task >> 1 : 0;
+            rsp[k] = task & 1;
+            int lx, ly;
+            ring_pos(site, lx, ly);
+            rfx[k] = lx + 1;
+            rfy[k] = ly + HY;
+            const int rgx = wrapi(X0 + lx, NX);
+            const int rgy = HY ? wrapi(Y0 + ly, NY) : 0;
+#pragma unroll
+            for (int a = 0; a < 2 * HY + 1; ++a) {
+                const int yy = HY ? wrapi(rgy + a - HY, NY) : 0;
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    roff[k][a][b] = (uint32_t)(yy * NX + wrapi(rgx + b - 1, NX)) * (uint32_t)sizeof(T);
+            }
+        }
+        const int own_fx = tx + 1, own_fy = ty + HY;
+        const uint32_t own_voff = (uint32_t)(gy * NX + gx) * (uint32_t)sizeof(T);
+        auto slot_of = [&](int m) { return (m - m0 + 1) & 3; };
+        auto bases = [&](int m, uint32_t (&pb)[3]) {
+            const int mm = wrapi(m, NM);
+            const uint32_t PB = P * (uint32_t)sizeof(T);
+            pb[0] = __builtin_amdgcn_readfirstlane((uint32_t)(mm == 0 ? NM - 1 : mm - 1) * PB);
+            pb[1] = __builtin_amdgcn_readfirstlane((uint32_t)mm * PB);
+            pb[2] = __builtin_amdgcn_readfirstlane((uint32_t)(mm == NM - 1 ? 0 : mm + 1) * PB);
+        };
+        auto ring_fill = [&](int m) {
+            uint32_t pb[3];
+            bases(m, pb);
+            const int slot = slot_of(m);
+#pragma unroll
+            for (int k = 0; k < RPT; ++k)
+                if (rok[k])
+                    lds[lidx(slot, rsp[k], rfy[k], rfx[k])] =
+                        pull_species(src, pbytes, rsp[k], pb, roff[k]);
+        };
+        auto own_fill = [&](int m, T (&v)[2][Q]) {
+            uint32_t pb[3];
+            bases(m, pb);
+            A dA, dB;
+            Base::pull(src, pbytes, pb, off, v, dA, dB);
+            const int slot = slot_of(m);
+            lds[lidx(slot, 0, own_fy, own_fx)] = dA;
+            lds[lidx(slot, 1, own_fy, own_fx)] = dB;
+        };
+
+        T r0[2][Q], r1[2][Q], r2[2][Q];
+        // prologue: densities of m0-1, pops (kept) and densities of m0, m0+1
+        own_fill(m0 - 1, r2);
+        ring_fill(m0 - 1);
+        own_fill(m0, r0);
+        ring_fill(m0);
+        own_fill(m0 + 1, r1);
+        ring_fill(m0 + 1);
+        __syncthreads();
+
+        for (int m = m0; m < m1; ++m) {
+            const bool more = m + 2 <= m1;
+            uint32_t pb2[3];
+            A d2A = A(0), d2B = A(0);
+            A rs[RPT];
+            if (more) {
+                // issue plane m+2 now; consumed after the collision of plane m
+                bases(m + 2, pb2);
+                Base::pull(src, pbytes, pb2, off, r2, d2A, d2B);
+#pragma unroll
+                for (int k = 0; k < RPT; ++k)
+                    rs[k] = rok[k] ? pull_species(src, pbytes, rsp[k], pb2, roff[k]) : A(0);
+            }
+            if (valid) {
+                const int km = slot_of(m);
+                A g[2][3];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    A gx_ = A(0), gy_ = A(0), gz_ = A(0);
+#pragma unroll
+                    for (int i = 1; i < Q; ++i) {
+                        const int slot = (km + Geo<Q>::dm(i)) & 3;
+                        const A r = lds[lidx(slot, s, own_fy + Geo<Q>::dy(i),
+                                              own_fx + Geo<Q>::dx(i))];
+                        const A wr = A(VSet<Q>::w(i)) * r;
+                        if (VSet<Q>::cx(i)) gx_ += VSet<Q>::cx(i) > 0 ? wr : -wr;
+                        if (VSet<Q>::cy(i)) gy_ += VSet<Q>::cy(i) > 0 ? wr : -wr;
+                        if (VSet<Q>::cz(i)) gz_ += VSet<Q>::cz(i) > 0 ? wr : -wr;
+                    }
+                    g[s][0] = gx_;
+                    g[s][1] = gy_;
+                    g[s][2] = gz_;
+                }
+                const double body = p.body_A != 0.0 ? kolmogorov(p, HY ? gy : m) : 0.0;
+                collide_store<Q, PR>(r0, g, p, body, dst, pbytes, own_voff,
+                                     __builtin_amdgcn_readfirstlane((uint32_t)m * P *
+                                                                    (uint32_t)sizeof(T)));
+            }
+            if (more) {
+                const int s2 = slot_of(m + 2);
+                lds[lidx(s2, 0, own_fy, own_fx)] = d2A;
+                lds[lidx(s2, 1, own_fy, own_fx)] = d2B;
+#pragma unroll
+                for (int k = 0; k < RPT; ++k)
+                    if (rok[k]) lds[lidx(s2, rsp[k], rfy[k], rfx[k])] = rs[k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    r0[s][i] = r1[s][i];
+                    r1[s][i] = r2[s][i];
+                }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Re-pull march.  Same tile / march / LDS ring as TileStep, but no plane is
+// held in registers across iterations: the densities of plane m+1 are summed
+// from pulled loads as they arrive, then plane m is pulled again (its reuse
+// distance is one plane iteration, a few tens of MB across the GPU, so it is
+// served by L2 / the 256 MB Infinity Cache rather than HBM) and collided.
+// Holding one plane instead of two halves the registers per thread and
+// doubles the waves, and with them the loads in flight per CU.
+// ---------------------------------------------------------------------------
+template <int Q, class PR, int TX, int TY>
+struct TileStepRepull {
+    using T = typename PR::T;
+    using A = typename PR::A;
+    using Base = TileStep<Q, PR, TX, TY>;
+    using Pipe = TileStepPipe<Q, PR, TX, TY>;
+    static constexpr int HY = Geo<Q>::HY;
+    static constexpr int FW = TX + 2;
+    static constexpr int FH = TY + 2 * HY;
+    static constexpr int NT = TX * TY;
+    static constexpr int RT = Pipe::RT;
+    static constexpr int RPT = Pipe::RPT;
+    static constexpr int LDS_ELEMS = Base::LDS_ELEMS;
+
+    // density of one species from Q pulled loads, summed as they arrive
+    __device__ static __forceinline__ A dens(const char* __restrict__ src, uint32_t plane_bytes,
+                                             int s, const uint32_t (&pb)[3],
+                                             const uint32_t (&off)[2 * HY + 1][3]) {
+        return Pipe::pull_species(src, plane_bytes, s, pb, off);
+    }
+
+    __device__ static __forceinline__ void run(const StepParams& p_in, int tile_x_in,
+                                               int tile_y_in, int chunk_in, A* __restrict__ lds) {
+        const StepParams p = uniform_params(p_in);
+        const int tile_x = (int)uni32((uint32_t)tile_x_in);
+        const int tile_y = (int)uni32((uint32_t)tile_y_in);
+        const int chunk = (int)uni32((uint32_t)chunk_in);
+        const char* __restrict__ src = static_cast<const char*>(p.src);
+        char* __restrict__ dst = static_cast<char*>(p.dst);
+        const uint32_t pbytes = p.N * (uint32_t)sizeof(T);
+        const int tid = threadIdx.x;
+        const int tx = tid % TX, ty = tid / TX;
+        const int X0 = tile_x * TX, Y0 = tile_y * TY;
+        const int m0 = chunk * p.mb;
+        const int m1 = min(m0 + p.mb, p.NM);
+        const int NX = p.NX, NY = p.NY, NM = p.NM;
+        const uint32_t P = p.P;
+
+        const int gx = wrapi(X0 + tx, NX);
+        const int gy = HY ? wrapi(Y0 + ty, NY) : 0;
+        const bool valid = (X0 + tx < NX) && (!HY || Y0 + ty < NY);
+        uint32_t off[2 * HY + 1][3];
+#pragma unroll
+        for (int a = 0; a < 2 * HY + 1; ++a) {
+            const int yy = HY ? wrapi(gy + a - HY, NY) : 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                off[a][b] = (uint32_t)(yy * NX + wrapi(gx + b - 1, NX)) * (uint32_t)sizeof(T);
+        }
+        uint32_t roff[RPT][2 * HY + 1][3];
+        int rfx[RPT], rfy[RPT], rsp[RPT];
+        bool rok[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int task = tid + k * NT;
+            rok[k] = task < RT;
+            const int site = rok[k] ? task >> 1 : 0;
+            rsp[k] = task & 1;
+            int lx, ly;
+            Pipe::ring_pos(site, lx, ly);
+            rfx[k] = lx + 1;
+            rfy[k] = ly + HY;
+            const int rgx = wrapi(X0 + lx, NX);
+            const int rgy = HY ? wrapi(Y0 + ly, NY) : 0;
+#pragma unroll
+            for (int a = 0; a < 2 * HY + 1; ++a) {
+                const int yy = HY ? wrapi(rgy + a - HY, NY) : 0;
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    roff[k][a][b] = (uint32_t)(yy * NX + wrapi(rgx + b - 1, NX)) * (uint32_t)sizeof(T);
+            }
+        }
+        const int own_fx = tx + 1, own_fy = ty + HY;
+        const uint32_t own_voff = (uint32_t)(gy * NX + gx) * (uint32_t)sizeof(T);
+        auto slot_of = [&](int m) { return (m - m0 + 1) & 3; };
+        auto bases = [&](int m, uint32_t (&pb)[3]) {
+            const int mm = wrapi(m, NM);
+            const uint32_t PB = P * (uint32_t)sizeof(T);
+            pb[0] = __builtin_amdgcn_readfirstlane((uint32_t)(mm == 0 ? NM - 1 : mm - 1) * PB);
+            pb[1] = __builtin_amdgcn_readfirstlane((uint32_t)mm * PB);
+            pb[2] = __builtin_amdgcn_readfirstlane((uint32_t)(mm == NM - 1 ? 0 : mm + 1) * PB);
+        };
+        // densities of plane m (interior and ring) into its LDS slot
+        auto dens_fill = [&](int m) {
+            uint32_t pb[3];
+            bases(m, pb);
+            const int slot = slot_of(m);
+#pragma unroll
+            for (int k = 0; k < RPT; ++k)
+                if (rok[k]) lds[Base::lidx(slot, rsp[k], rfy[k], rfx[k])] = dens(src, pbytes, rsp[k], pb, roff[k]);
+            lds[Base::lidx(slot, 0, own_fy, own_fx)] = dens(src, pbytes, 0, pb, off);
+            lds[Base::lidx(slot, 1, own_fy, own_fx)] = dens(src, pbytes, 1, pb, off);
+        };
+
+        dens_fill(m0 - 1);
+        dens_fill(m0);
+        T cur[2][Q];
+        for (int m = m0; m < m1; ++m) {
+            dens_fill(m + 1);
+            // plane m again, for the collision (cache-served)
+            uint32_t pb[3];
+            bases(m, pb);
+            A dA, dB;
+            Base::pull(src, pbytes, pb, off, cur, dA, dB);
+            __syncthreads();
+            if (valid) {
+                const int km = slot_of(m);
+                A g[2][3];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    A gx_ = A(0), gy_ = A(0), gz_ = A(0);
+#pragma unroll
+                    for (int i = 1; i < Q; ++i) {
+                        const int slot = (km + Geo<Q>::dm(i)) & 3;
+                        const A r = lds[Base::lidx(slot, s, own_fy + Geo<Q>::dy(i),
+                                                    own_fx + Geo<Q>::dx(i))];
+                        const A wr = A(VSet<Q>::w(i)) * r;
+                        if (VSet<Q>::cx(i)) gx_ += VSet<Q>::cx(i) > 0 ? wr : -wr;
+                        if (VSet<Q>::cy(i)) gy_ += VSet<Q>::cy(i) > 0 ? wr : -wr;
+                        if (VSet<Q>::cz(i)) gz_ += VSet<Q>::cz(i) > 0 ? wr : -wr;
+                    }
+                    g[s][0] = gx_;
+                    g[s][1] = gy_;
+                    g[s][2] = gz_;
+                }
+                const double body = p.body_A != 0.0 ? kolmogorov(p, HY ? gy : m) : 0.0;
+                collide_store<Q, PR>(cur, g, p, body, dst, pbytes, own_voff,
+                                     __builtin_amdgcn_readfirstlane((uint32_t)m * P *
+                                                                    (uint32_t)sizeof(T)));
+            }
         }
     }
 };

@@ -38,6 +38,8 @@ bool tile_supported(int Q, int tx, int ty);
 
 // single-lattice launches
 hipError_t launch_fused(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s);
+hipError_t launch_repull(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s);
+hipError_t launch_pipe(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s);
 hipError_t launch_twopass(int Q, int prec, const StepParams& p, void* psi, hipStream_t s);
 hipError_t launch_init(int Q, int prec, void* f, const double* rho, const double* u, int nx,
                        int ny, int nz, const double* rho_ref, hipStream_t s);

@@ -98,6 +98,113 @@ hipError_t launch_fused(int Q, int prec, int tx, int ty, const StepParams& p, hi
                      : launch_fused_p<PF32S>(Q, tx, ty, p, s);
 }
 
+// Pipelined march: three register planes; one wave per SIMD for D3Q19 FP64,
+// two for D3Q19 FP32 and D2Q9 FP64, three for D2Q9 FP32.
+template <int Q, class PR>
+struct PipeWaves {
+    static constexpr int value = PR::shifted ? (Q == 19 ? 2 : 3) : (Q == 19 ? 1 : 2);
+};
+
+template <int Q, class PR, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+    __attribute__((amdgpu_waves_per_eu(PipeWaves<Q, PR>::value))) k_step_pipe(StepParams p) {
+    using TS = TileStepPipe<Q, PR, TX, TY>;
+    __shared__ typename PR::A lds[TS::LDS_ELEMS];
+    const int w = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int tiles = p.ntx * p.nty;
+    const int chunk = w / tiles;
+    const int t = w - chunk * tiles;
+    TS::run(p, t % p.ntx, t / p.ntx, chunk, lds);
+}
+
+template <int Q, class PR, int TX, int TY>
+static hipError_t launch_pipe_t(const StepParams& p, hipStream_t s) {
+    const unsigned nblk = (unsigned)p.ntx * p.nty * p.nchunks;
+    hipLaunchKernelGGL((k_step_pipe<Q, PR, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, p);
+    return hipGetLastError();
+}
+
+template <class PR>
+static hipError_t launch_pipe_p(int Q, int tx, int ty, const StepParams& p, hipStream_t s) {
+    if (Q == 9) {
+        switch (tx) {
+            case 64: return launch_pipe_t<9, PR, 64, 1>(p, s);
+            case 128: return launch_pipe_t<9, PR, 128, 1>(p, s);
+            case 256: return launch_pipe_t<9, PR, 256, 1>(p, s);
+            case 512: return launch_pipe_t<9, PR, 512, 1>(p, s);
+        }
+    } else {
+        const int key = tx * 1000 + ty;
+        switch (key) {
+            case 32004: return launch_pipe_t<19, PR, 32, 4>(p, s);
+            case 64004: return launch_pipe_t<19, PR, 64, 4>(p, s);
+            case 32008: return launch_pipe_t<19, PR, 32, 8>(p, s);
+            case 64008: return launch_pipe_t<19, PR, 64, 8>(p, s);
+            case 16016: return launch_pipe_t<19, PR, 16, 16>(p, s);
+            case 32016: return launch_pipe_t<19, PR, 32, 16>(p, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pipe(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s) {
+    return prec == 0 ? launch_pipe_p<PF64>(Q, tx, ty, p, s) : launch_pipe_p<PF32S>(Q, tx, ty, p, s);
+}
+
+
+// Re-pull march: one register plane; three waves per SIMD for FP64, four for FP32.
+template <int Q, class PR>
+struct RepullWaves {
+    static constexpr int value = PR::shifted ? 4 : 3;
+};
+
+template <int Q, class PR, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+    __attribute__((amdgpu_waves_per_eu(RepullWaves<Q, PR>::value))) k_step_repull(StepParams p) {
+    using TS = TileStepRepull<Q, PR, TX, TY>;
+    __shared__ typename PR::A lds[TS::LDS_ELEMS];
+    const int w = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int tiles = p.ntx * p.nty;
+    const int chunk = w / tiles;
+    const int t = w - chunk * tiles;
+    TS::run(p, t % p.ntx, t / p.ntx, chunk, lds);
+}
+
+template <int Q, class PR, int TX, int TY>
+static hipError_t launch_repull_t(const StepParams& p, hipStream_t s) {
+    const unsigned nblk = (unsigned)p.ntx * p.nty * p.nchunks;
+    hipLaunchKernelGGL((k_step_repull<Q, PR, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, p);
+    return hipGetLastError();
+}
+
+template <class PR>
+static hipError_t launch_repull_p(int Q, int tx, int ty, const StepParams& p, hipStream_t s) {
+    if (Q == 9) {
+        switch (tx) {
+            case 64: return launch_repull_t<9, PR, 64, 1>(p, s);
+            case 128: return launch_repull_t<9, PR, 128, 1>(p, s);
+            case 256: return launch_repull_t<9, PR, 256, 1>(p, s);
+            case 512: return launch_repull_t<9, PR, 512, 1>(p, s);
+        }
+    } else {
+        const int key = tx * 1000 + ty;
+        switch (key) {
+            case 32004: return launch_repull_t<19, PR, 32, 4>(p, s);
+            case 64004: return launch_repull_t<19, PR, 64, 4>(p, s);
+            case 32008: return launch_repull_t<19, PR, 32, 8>(p, s);
+            case 64008: return launch_repull_t<19, PR, 64, 8>(p, s);
+            case 16016: return launch_repull_t<19, PR, 16, 16>(p, s);
+            case 32016: return launch_repull_t<19, PR, 32, 16>(p, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_repull(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s) {
+    return prec == 0 ? launch_repull_p<PF64>(Q, tx, ty, p, s)
+                     : launch_repull_p<PF32S>(Q, tx, ty, p, s);
+}
+
 // ---------------------------------------------------------------------------
 // Site helpers for the simple (one thread per site) kernels.
 // ---------------------------------------------------------------------------

@@ -135,6 +135,8 @@ StepParams sc_step_params(const lbm_sc* h, int parity) {
 hipError_t sc_launch_step(lbm_sc* h, int parity, hipStream_t s) {
     const StepParams sp = sc_step_params(h, parity);
     if (h->variant == 1) return launch_twopass(h->Q, h->p.precision, sp, h->psi, s);
+    if (h->variant == 2) return launch_pipe(h->Q, h->p.precision, h->tx, h->ty, sp, s);
+    if (h->variant == 3) return launch_repull(h->Q, h->p.precision, h->tx, h->ty, sp, s);
     return launch_fused(h->Q, h->p.precision, h->tx, h->ty, sp, s);
 }
 
@@ -528,7 +530,7 @@ int lbm_sc_time_steps(lbm_sc* h, int n, float* ms) {
 
 int lbm_sc_set_kernel(lbm_sc* h, int variant, int tx, int ty, int mb) {
     CHECK_H(h);
-    if (variant != 0 && variant != 1) return LBM_EINVAL;
+    if (variant < 0 || variant > 3) return LBM_EINVAL;
     if (h->Q == 9 && ty != 1) return LBM_EINVAL;
     if (!tile_supported(h->Q, tx, ty)) return LBM_EINVAL;
     if (mb < 1) return LBM_EINVAL;

@@ -28,7 +28,9 @@ def test_cfg1_d2q9_drop_100_steps():
 
 
 @pytest.mark.parametrize("kernel", [(0, 64, 1, 5), (0, 128, 1, 64), (0, 256, 1, 7),
-                                    (0, 512, 1, 3), (1, 64, 1, 8)])
+                                    (0, 512, 1, 3), (1, 64, 1, 8), (2, 64, 1, 5), (2, 128, 1, 1),
+                                    (2, 256, 1, 37), (2, 512, 1, 2), (3, 64, 1, 5),
+                                    (3, 128, 1, 1), (3, 256, 1, 37), (3, 512, 1, 2)])
 def test_d2q9_ragged_tiles_and_variants(kernel):
     """100 x 37 (ragged against every tile), unequal tau, body force."""
     fl = sc_inputs.drop(100, 37, 1, radius=9, seed=11)
@@ -47,7 +49,10 @@ def test_d3q19_drop_32cube_100_steps():
 
 
 @pytest.mark.parametrize("kernel", [(0, 32, 4, 3), (0, 64, 4, 11), (0, 32, 8, 4), (0, 64, 8, 2),
-                                    (0, 16, 16, 5), (0, 32, 16, 11), (1, 32, 4, 8)])
+                                    (0, 16, 16, 5), (0, 32, 16, 11), (1, 32, 4, 8), (2, 32, 4, 3),
+                                    (2, 64, 4, 11), (2, 32, 8, 1), (2, 64, 8, 2), (2, 16, 16, 5),
+                                    (2, 32, 16, 11), (3, 32, 4, 3), (3, 64, 4, 11), (3, 32, 8, 1),
+                                    (3, 64, 8, 2), (3, 16, 16, 5), (3, 32, 16, 11)])
 def test_d3q19_ragged_tiles_and_variants(kernel):
     """37 x 29 x 11 spinodal (ragged in x, y and the march), unequal tau."""
     fl = sc_inputs.spinodal(37, 29, 11, seed=12)
