@@ -76,6 +76,72 @@ def cpu_baseline(fields):
                       f"{dt:.1f} s, single-threaded C oracle, -O2, no FMA contraction)"}
 
 
+def batch_leg(n_jobs: int, steps: int, epoch: int):
+    """64 independent D2Q9 drop lattices (L ~ U{64..512}, seed 4), FP32 shifted,
+    advanced `steps` steps each: one launch per lattice per step, one launch per
+    step for all lattices (graph-replayed), and one persistent launch per epoch,
+    after the batch autotuner picked the block shape and march chunks."""
+    import torch
+    import sc_inputs
+    from paper_1112_5547_amd import Batch, Lattice, autotune
+    jobs = sc_inputs.batch_jobs(n_jobs, seed=4, steps=steps)
+    tuned = autotune.tune_batch(jobs, precision="fp32_shifted", mode="persistent", epoch=50)
+    work = sum(j.sites * j.steps for j in jobs)
+    out = {"workload": f"{n_jobs} D2Q9 drop lattices L~U{{64..512}} (seed 4), FP32 shifted, "
+                       f"{steps} steps each, epochs of {epoch}",
+           "site_updates": work, "tiles": tuned}
+    for mode in ("per_lattice", "fused", "persistent"):
+        lats = []
+        for j in jobs:
+            lat = Lattice(9, j.nx, j.ny, 1, tau_A=j.tau, G=j.G, precision="fp32_shifted")
+            fl = j.fields()
+            lat.init(fl.rho_A, fl.rho_B)
+            lats.append(lat)
+        b = Batch()
+        b.set_tiles(tuned["tx9"], tuned["tx19"], tuned["ty19"], tuned["mb9"], tuned["mb19"])
+        for lat, j in zip(lats, jobs):
+            b.add(lat, j.steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while len(b.poll()) < len(lats):
+            b.run(epoch, mode)
+        dt = time.perf_counter() - t0
+        out[mode] = {"seconds": round(dt, 4), "mlups": round(work / dt / 1e6, 1)}
+        for lat in lats:
+            b.remove(lat)
+            lat.close()
+        b.close()
+    out["speedup_persistent_vs_per_lattice"] = round(
+        out["persistent"]["mlups"] / out["per_lattice"]["mlups"], 2)
+    out["speedup_fused_vs_per_lattice"] = round(
+        out["fused"]["mlups"] / out["per_lattice"]["mlups"], 2)
+    return out
+
+
+def serve_leg(n_jobs: int, capacity_mlups: float, budget_gb: float, epoch: int):
+    """Poisson stream of drop / spinodal jobs (seed 5): 70 % D2Q9 drops
+    L~U{64..512}, 30 % D3Q19 L~U{64..256} (half drops, half spinodal), steps
+    U{500..5000}, FP32 shifted; offered load 0.7 x the measured FP32 capacity;
+    served with continuous batching, and sequentially (one job at a time, one
+    lattice per launch) on the same arrivals."""
+    import sc_inputs
+    from paper_1112_5547_amd.serve import GpuBackend, Server, offered_rate, sequential_baseline
+    probe = sc_inputs.serving_jobs(n_jobs, seed=5, rate=1.0)
+    rate = offered_rate(probe, capacity_mlups, load=0.7)
+    jobs = sc_inputs.serving_jobs(n_jobs, seed=5, rate=rate)
+    rep = Server(hbm_budget=int(budget_gb * 1e9), epoch_steps=epoch, mode="persistent",
+                 backend=GpuBackend("fp32_shifted")).run(jobs)
+    served = rep.summary()
+    seq = sequential_baseline(jobs, backend=GpuBackend("fp32_shifted"))
+    r3 = lambda v: round(v, 3) if isinstance(v, float) else v
+    return {"workload": f"{n_jobs} Poisson jobs (seed 5), 70% D2Q9 64^2-512^2 drops, 30% D3Q19 "
+                        f"64^3-256^3 drops/spinodal, 500-5000 steps, FP32 shifted, "
+                        f"offered load 0.7 x {capacity_mlups:.0f} MLUPS, budget {budget_gb:g} GB",
+            "arrival_rate_per_s": round(rate, 4),
+            "served": {k: r3(v) for k, v in served.items()},
+            "sequential": {k: r3(v) for k, v in seq.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +150,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-lattices leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-jobs leg")
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--serve-jobs", type=int, default=64)
     ap.add_argument("--kernel", type=str, default=None,
                     help="variant,tx,ty,mb of the FP64 step (default: tuned table)")
     args = ap.parse_args()
@@ -105,7 +175,7 @@ def main():
     mlups = n * args.steps / r64["wall_s"] / 1e6
     ach = b_alg(Q19, 8) * n / (r64["kernel_ms"] * 1e-3) / 1e9
     out = {
-        "metric": "MLUPS + % HBM roofline, D3Q19 2-comp SC 256^3",
+        "metric": "MLUPS + % HBM roofline, D3Q19 2-comp SC 256^3; served-job p50/p99 latency",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -138,6 +208,14 @@ def main():
             "kernel": list(r32["kernel"]),
             "mass_drift_A": (r32["T"]["mass_A"] - r32["T0"]["mass_A"]) / r32["T0"]["mass_A"],
         }
+    if not args.no_batch:
+        out["batched"] = batch_leg(64, args.batch_steps, epoch=250)
+    if not args.no_serve:
+        cap = out.get("fp32_shifted", {}).get("value", 10000.0)
+        out["served"] = serve_leg(args.serve_jobs, cap, budget_gb=96.0, epoch=250)
+        out["metric_served"] = {"p50_latency_s": out["served"]["served"]["p50_latency_s"],
+                                "p99_latency_s": out["served"]["served"]["p99_latency_s"],
+                                "aggregate_mlups": out["served"]["served"]["aggregate_mlups"]}
     if not args.no_copy:
         out["copy_ceiling_GBps"] = round(copy_bench(2 << 30, reps=10), 1)
     if not args.no_cpu:

@@ -127,16 +127,64 @@ if __name__ == "__main__":
     ap.add_argument("specs", nargs="+", help="q:nx:ny:nz:precision, e.g. 19:256:256:256:fp64")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--store", action="store_true")
+    ap.add_argument("--table", default=CACHE, help="JSON table to update (default: packaged)")
     a = ap.parse_args()
     specs = []
     for s in a.specs:
         q, x, y, z, p = s.split(":")
         specs.append((int(q), int(x), int(y), int(z), p))
-    table = load()
+    table = load(a.table)
     for spec in specs:
         e = tune(*spec[:4], precision=spec[4], steps=a.steps, verbose=True)
         best = {k: v for k, v in e.items() if k != "candidates"}
         print(json.dumps(best), flush=True)
         table[_key(*spec)] = best
     if a.store:
-        save(table)
+        save(table, a.table)
+
+
+BATCH_CFGS = [(256, 64, 4), (256, 32, 8), (512, 64, 8), (128, 32, 4)]
+
+
+def tune_batch(jobs, *, precision: str = "fp32_shifted", mode: str = "persistent",
+               epoch: int = 50, mbs=(0, 64, 256), verbose: bool = False) -> dict:
+    """Chooses the shared block shape (D2Q9 tile width = D3Q19 tile area) and
+    the march chunks of a batch by timing one epoch of the given jobs on
+    scratch lattices for each candidate.  Returns the fastest as
+    {"tx9", "tx19", "ty19", "mb9", "mb19", "ms"}."""
+    import time
+
+    import torch
+
+    from .batch import Batch
+    lats = []
+    for j in jobs:
+        lat = Lattice(j.lattice, j.nx, j.ny, j.nz, tau_A=j.tau, G=j.G, precision=precision)
+        fl = j.fields()
+        lat.init(fl.rho_A, fl.rho_B)
+        lats.append(lat)
+    best = None
+    for (nt, tx19, ty19) in BATCH_CFGS:
+        for mb in mbs:
+            b = Batch()
+            b.set_tiles(nt, tx19, ty19, mb, mb)
+            for lat in lats:
+                b.add(lat, 10 ** 9)
+            b.run(epoch, mode)       # warm-up and graph capture
+            b.poll()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.run(epoch, mode)
+            b.poll()
+            ms = (time.perf_counter() - t0) * 1e3
+            for lat in lats:
+                b.remove(lat)
+            b.close()
+            cand = {"tx9": nt, "tx19": tx19, "ty19": ty19, "mb9": mb, "mb19": mb, "ms": ms}
+            if verbose:
+                print("  batch", cand, flush=True)
+            if best is None or ms < best["ms"]:
+                best = cand
+    for lat in lats:
+        lat.close()
+    return best

@@ -173,15 +173,14 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
                                              kBufWord3);
 }
 
-template <typename T>
-__device__ __forceinline__ T buf_load(rsrc_t r, uint32_t voff, uint32_t soff);
-template <>
-__device__ __forceinline__ double buf_load<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-template <>
-__device__ __forceinline__ float buf_load<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+// AUX is the cache policy: 0 = default, 2 = nontemporal (streamed through L2
+// at low retention, for data no other block reads again).
+template <typename T, int AUX = 0>
+__device__ __forceinline__ T buf_load(rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
 }
 
 // nontemporal store (aux bit 1: streaming, do not keep in L2)
@@ -330,11 +329,22 @@ struct TileStep {
         return ((slot * 2 + s) * FH + fy) * FW + fx;
     }
 
+    // True for waves whose tile rows are all at least two rows from the
+    // tile's y edges: no neighbouring tile's ring pulls read their sites, so
+    // their loads stream (nontemporal) and leave L2 to the boundary rows.
+    __device__ static __forceinline__ bool streaming_wave() {
+        if (!HY || TY < 5) return false;
+        const int w0 = (int)(threadIdx.x & ~63u);
+        const int ty_lo = w0 / TX, ty_hi = (w0 + 63) / TX;
+        return ty_lo >= 2 && ty_hi <= TY - 3;
+    }
+
     // Pull the 2Q populations of one site of plane m into v and return the
     // two species' density sums (delta densities when shifted).  pb holds the
     // byte offsets of planes m-1, m, m+1 (uniform across the block) and off
     // the lane's nine in-plane byte offsets (N * sizeof(T) < 2^32), so every
     // load is a scalar base plus one precomputed 32-bit lane offset.
+    template <int AUX = 0>
     __device__ static __forceinline__ void pull(const char* __restrict__ src, uint32_t plane_bytes,
                                                 const uint32_t (&pb)[3],
                                                 const uint32_t (&off)[2 * HY + 1][3],
@@ -347,8 +357,8 @@ struct TileStep {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const rsrc_t r = make_rsrc(src + (size_t)(s * Q + i) * plane_bytes, plane_bytes);
-                v[s][i] = buf_load<T>(r, off[HY - Geo<Q>::dy(i)][1 - Geo<Q>::dx(i)],
-                                      pb[1 - Geo<Q>::dm(i)]);
+                v[s][i] = buf_load<T, AUX>(r, off[HY - Geo<Q>::dy(i)][1 - Geo<Q>::dx(i)],
+                                           pb[1 - Geo<Q>::dm(i)]);
             }
         __builtin_amdgcn_sched_group_barrier(0x020, 2 * Q, 0);  // 2Q VMEM reads first
         A acc[2];
@@ -431,6 +441,7 @@ struct TileStep {
         T cur[2][Q], nxt[2][Q];
         A dA, dB;
         uint32_t pb[3];
+        const bool stream = streaming_wave();
 
         auto plane_bases = [&](int m) {
             const int mm = wrapi(m, NM);
@@ -452,7 +463,10 @@ struct TileStep {
             // keep the ring's loads from overlapping the plane kept in
             // registers: bounds the live registers to two planes
             __builtin_amdgcn_sched_barrier(0);
-            pull(src, pbytes, pb, off, nxt, dA, dB);
+            if (stream)
+                pull<2>(src, pbytes, pb, off, nxt, dA, dB);
+            else
+                pull<0>(src, pbytes, pb, off, nxt, dA, dB);
             lds[lidx(slot, 0, own_fy, own_fx)] = dA;
             lds[lidx(slot, 1, own_fy, own_fx)] = dB;
         };
@@ -647,7 +661,7 @@ struct TileStepPipe {
             uint32_t pb[3];
             bases(m, pb);
             A dA, dB;
-            Base::pull(src, pbytes, pb, off, v, dA, dB);
+            Base::template pull<0>(src, pbytes, pb, off, v, dA, dB);
             const int slot = slot_of(m);
             lds[lidx(slot, 0, own_fy, own_fx)] = dA;
             lds[lidx(slot, 1, own_fy, own_fx)] = dB;
@@ -671,7 +685,7 @@ struct TileStepPipe {
             if (more) {
                 // issue plane m+2 now; consumed after the collision of plane m
                 bases(m + 2, pb2);
-                Base::pull(src, pbytes, pb2, off, r2, d2A, d2B);
+                Base::template pull<0>(src, pbytes, pb2, off, r2, d2A, d2B);
 #pragma unroll
                 for (int k = 0; k < RPT; ++k)
                     rs[k] = rok[k] ? pull_species(src, pbytes, rsp[k], pb2, roff[k]) : A(0);
@@ -833,7 +847,7 @@ struct TileStepRepull {
             uint32_t pb[3];
             bases(m, pb);
             A dA, dB;
-            Base::pull(src, pbytes, pb, off, cur, dA, dB);
+            Base::template pull<2>(src, pbytes, pb, off, cur, dA, dB);  // last use of plane m
             __syncthreads();
             if (valid) {
                 const int km = slot_of(m);

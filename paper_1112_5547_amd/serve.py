@@ -109,6 +109,9 @@ class GpuBackend:
         from .lattice import Lattice
         lat = Lattice(job.lattice, job.nx, job.ny, job.nz, tau_A=job.tau, G=job.G,
                       precision=self.precision)
+        if self.tuned:  # solo launches use the autotuned kernel (batches their own tiles)
+            from . import autotune
+            autotune.apply(lat)
         fl = job.fields()
         lat.init(fl.rho_A, fl.rho_B)
         if fl.radius > 0:
@@ -129,7 +132,7 @@ class GpuBackend:
 
 
 class Server:
-    def __init__(self, hbm_budget: int, *, epoch_steps: int = 200, mode: str = "persistent",
+    def __init__(self, hbm_budget: int = 0, *, epoch_steps: int = 200, mode: str = "persistent",
                  max_resident: int = 256, backend=None, clock=None,
                  keep_populations: bool = False, admit_hook: Optional[Callable] = None):
         self.budget = int(hbm_budget)
@@ -162,11 +165,12 @@ class Server:
             k = 0
             while k < len(queue):
                 job = queue[k]
-                if need[job.job_id] > self.budget:
+                if self.budget and need[job.job_id] > self.budget:
                     queue.pop(k)           # can never fit: report, do not block the queue
                     refused += 1
                     continue
-                if len(resident) < self.max_resident and used + need[job.job_id] <= self.budget:
+                fits = not self.budget or used + need[job.job_id] <= self.budget
+                if len(resident) < self.max_resident and fits:
                     lat = be.make_lattice(job)
                     if not batch.add(lat, job.steps):
                         be.release(lat)

@@ -164,17 +164,23 @@ class JobSpec:
         return spinodal(self.nx, self.ny, self.nz, seed=self.seed)
 
 
+def _r_lo(L: int) -> float:
+    """Smallest drop radius drawn: 8 sites, less on lattices under 64 sites."""
+    return min(8.0, L / 8.0)
+
+
 def batch_jobs(n_jobs: int = 64, *, seed: int = 4, l_min: int = 64, l_max: int = 512,
                steps: int = 2000) -> List[JobSpec]:
     """Independent square D2Q9 drop lattices of uneven sizes.
 
-    L ~ U{l_min..l_max}, R ~ U[8, L/4], G ~ U[1.2, 1.6], tau ~ U[0.6, 1.5].
+    L ~ U{l_min..l_max}, R ~ U[8, L/4] (8 -> L/8 below L = 64), G ~ U[1.2, 1.6],
+    tau ~ U[0.6, 1.5].
     """
     rng = np.random.default_rng(seed)
     jobs = []
     for k in range(n_jobs):
         L = int(rng.integers(l_min, l_max + 1))
-        R = float(rng.uniform(8.0, L / 4.0))
+        R = float(rng.uniform(_r_lo(L), L / 4.0))
         G = float(rng.uniform(1.2, 1.6))
         tau = float(rng.uniform(0.6, 1.5))
         jobs.append(JobSpec(k, 9, L, L, 1, tau, G, steps, "drop", R,
@@ -205,7 +211,7 @@ def serving_jobs(n_jobs: int = 200, *, seed: int = 5, rate: float = 1.0,
         js = int(rng.integers(0, 2**31 - 1))
         if rng.uniform() >= frac_3d:
             L = int(rng.integers(l2[0], l2[1] + 1))
-            R = float(rng.uniform(8.0, L / 4.0))
+            R = float(rng.uniform(_r_lo(L), L / 4.0))
             G = float(rng.uniform(1.2, 1.6))
             tau = float(rng.uniform(0.6, 1.5))
             jobs.append(JobSpec(k, 9, L, L, 1, tau, G, steps, "drop", R, js,
@@ -213,7 +219,7 @@ def serving_jobs(n_jobs: int = 200, *, seed: int = 5, rate: float = 1.0,
         else:
             L = int(rng.integers(l3[0], l3[1] + 1))
             if rng.uniform() < 0.5:
-                R = float(rng.uniform(8.0, L / 4.0))
+                R = float(rng.uniform(_r_lo(L), L / 4.0))
                 jobs.append(JobSpec(k, 19, L, L, L, 1.0, 1.3, steps, "drop", R, js,
                                     float(arrivals[k])))
             else:

@@ -1,0 +1,52 @@
+"""Continuous batching on the GPU: every served job's result equals its solo
+run bitwise, jobs overlap on the device, the memory budget forces queueing,
+and a diverging job is reported without disturbing the others."""
+import numpy as np
+import pytest
+
+import sc_inputs
+from gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _jobs(n, seed, rate):
+    return sc_inputs.serving_jobs(n, seed=seed, rate=rate, step_range=(40, 400), l2=(32, 160),
+                                  l3=(16, 40), frac_3d=0.35)
+
+
+@pytest.mark.parametrize("precision,mode", [("fp32_shifted", "persistent"), ("fp64", "fused")])
+def test_served_results_equal_solo_runs(precision, mode):
+    from paper_1112_5547_amd import Lattice
+    from paper_1112_5547_amd.serve import GpuBackend, Server
+    jobs = _jobs(14, seed=31, rate=400.0)
+    be = GpuBackend(precision=precision)
+    budget = sum(sorted(be.bytes_needed(j) for j in jobs)[-4:])  # forces queueing
+    say(f"serve 14 jobs {precision} {mode}, budget {budget}")
+    rep = Server(hbm_budget=budget, epoch_steps=64, mode=mode, backend=be,
+                 keep_populations=True).run(jobs)
+    s = rep.summary()
+    assert s["jobs"] == len(jobs) and s["nonfinite"] == 0 and s["refused"] == 0
+    assert s["max_resident"] >= 2
+    for r in rep.results:
+        job = jobs[r.job_id]
+        say(f"solo job {job.job_id} q={job.lattice} {job.nx}x{job.ny}x{job.nz} {job.steps} steps")
+        lat = Lattice(job.lattice, job.nx, job.ny, job.nz, tau_A=job.tau, G=job.G,
+                      precision=precision)
+        fl = job.fields()
+        lat.init(fl.rho_A, fl.rho_B)
+        lat.step(job.steps)
+        assert np.array_equal(r.populations, lat.get_populations()), job
+        lat.close()
+
+
+def test_diverging_job_is_evicted_and_others_finish():
+    from paper_1112_5547_amd.serve import GpuBackend, Server
+    jobs = _jobs(6, seed=32, rate=1000.0)
+    jobs[3].G, jobs[3].tau, jobs[3].steps = 40.0, 0.51, 200
+    say("serve 6 jobs with one diverging")
+    rep = Server(hbm_budget=0, epoch_steps=50, mode="persistent",
+                 backend=GpuBackend("fp32_shifted")).run(jobs)
+    by_id = {r.job_id: r for r in rep.results}
+    assert by_id[3].status == "nonfinite"
+    assert all(r.status == "ok" for r in rep.results if r.job_id != 3)

@@ -1,0 +1,180 @@
+"""Serving-loop logic on the CPU: an oracle-driven backend and a simulated
+clock stand in for the GPU library, so admission by memory budget, epochs,
+joins between epochs, read-out, refusal and latency accounting are tested
+without a device.  Results must equal each job's solo oracle run bitwise
+(the backend advances every member with the same oracle code)."""
+import numpy as np
+import pytest
+
+import oracle
+import sc_inputs
+from paper_1112_5547_amd.serve import Server, offered_rate
+
+
+class SimClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self):
+        return self.t
+
+    def sleep_until(self, t):
+        self.t = max(self.t, t)
+
+    def advance(self, dt):
+        self.t += dt
+
+
+class FakeLattice:
+    def __init__(self, job):
+        self.job = job
+        self.q = job.lattice
+        self.shape = (job.nz, job.ny, job.nx)
+        fl = job.fields()
+        self.f = oracle.init(job.lattice, fl.rho_A, fl.rho_B)
+        self.steps_done = 0
+
+    def advance(self, n):
+        if n > 0:
+            self.f = oracle.run(self.f, self.job.tau, self.job.tau, self.job.G, n)
+            self.steps_done += n
+
+
+class FakeBatch:
+    """Members advance by up to epoch steps per run; the clock moves by the
+    epoch's site updates over a fixed capacity (site updates per second)."""
+
+    def __init__(self, budget, clock, capacity, bytes_of, log):
+        self.budget, self.clock, self.capacity = budget, clock, capacity
+        self.bytes_of, self.log = bytes_of, log
+        self.members = {}
+        self.used = 0
+
+    def add(self, lat, steps):
+        b = self.bytes_of(lat.job)
+        if self.budget and self.used + b > self.budget:
+            return False
+        self.members[id(lat)] = [lat, steps]
+        self.used += b
+        self.log.append(("used", self.used))
+        return True
+
+    def remove(self, lat):
+        self.members.pop(id(lat))
+        self.used -= self.bytes_of(lat.job)
+
+    def run(self, epoch, mode):
+        work = 0.0
+        for m in self.members.values():
+            k = min(epoch, m[1])
+            m[0].advance(k)
+            m[1] -= k
+            work += k * np.prod(m[0].shape)
+        self.clock.advance(work / self.capacity + 1e-4)
+        self.log.append(("epoch", self.clock.now(), len(self.members)))
+
+    def poll(self):
+        return [m[0] for m in self.members.values() if m[1] == 0]
+
+
+class FakeBackend:
+    def __init__(self, clock, capacity=2e6):
+        self.clock, self.capacity, self.log = clock, capacity, []
+
+    def bytes_needed(self, job):
+        return 2 * 2 * job.lattice * job.sites * 4       # FP32 ping-pong populations
+
+    def make_lattice(self, job):
+        return FakeLattice(job)
+
+    def make_batch(self, budget):
+        return FakeBatch(budget, self.clock, self.capacity, self.bytes_needed, self.log)
+
+    def finish(self, lat, keep):
+        rho = lat.f.sum(axis=1)
+        bad = int((~np.isfinite(rho)).sum())
+        return {"n_nonfinite": bad, "mass_A": float(rho[0].sum())}, (lat.f.copy() if keep else None)
+
+    def release(self, lat):
+        lat.f = None
+
+
+def _jobs(n=10, seed=21, rate=40.0):
+    return sc_inputs.serving_jobs(n, seed=seed, rate=rate, step_range=(5, 40), l2=(8, 20),
+                                  l3=(4, 7), frac_3d=0.3)
+
+
+def test_every_job_completes_with_its_solo_result():
+    clock = SimClock()
+    be = FakeBackend(clock)
+    jobs = _jobs()
+    rep = Server(hbm_budget=0, epoch_steps=8, backend=be, clock=clock,
+                 keep_populations=True).run(jobs)
+    assert len(rep.results) == len(jobs) and rep.refused == 0
+    for r, job in zip(rep.results, sorted(jobs, key=lambda j: j.job_id)):
+        assert r.job_id == job.job_id and r.status == "ok"
+        fl = job.fields()
+        solo = oracle.run(oracle.init(job.lattice, fl.rho_A, fl.rho_B), job.tau, job.tau, job.G,
+                          job.steps)
+        assert np.array_equal(r.populations, solo)
+        assert r.arrival <= r.admitted <= r.completed
+    s = rep.summary()
+    assert s["jobs"] == len(jobs) and s["p99_latency_s"] >= s["p50_latency_s"] > 0
+
+
+def test_budget_is_never_exceeded_and_forces_queueing():
+    clock = SimClock()
+    be = FakeBackend(clock)
+    jobs = _jobs(14, seed=5, rate=1000.0)      # near-simultaneous arrivals
+    budget = max(be.bytes_needed(j) for j in jobs) * 2
+    rep = Server(hbm_budget=budget, epoch_steps=8, backend=be, clock=clock).run(jobs)
+    used = [u for tag, u in ((e[0], e[1]) for e in be.log) if tag == "used"]
+    assert max(used) <= budget
+    assert len(rep.results) == len(jobs)
+    assert rep.summary()["max_queue"] > 0       # someone had to wait for memory
+
+
+def test_jobs_that_can_never_fit_are_refused_without_blocking():
+    clock = SimClock()
+    be = FakeBackend(clock)
+    jobs = _jobs(8, seed=9)
+    big = max(jobs, key=lambda j: j.sites)
+    budget = be.bytes_needed(big) - 1
+    rep = Server(hbm_budget=budget, epoch_steps=8, backend=be, clock=clock).run(jobs)
+    too_big = [j for j in jobs if be.bytes_needed(j) > budget]
+    assert rep.refused == len(too_big) >= 1
+    assert len(rep.results) == len(jobs) - len(too_big)
+
+
+def test_arrivals_during_an_epoch_join_at_the_next_boundary():
+    clock = SimClock()
+    be = FakeBackend(clock, capacity=1e4)       # slow device: long epochs
+    jobs = _jobs(6, seed=3, rate=200.0)
+    rep = Server(hbm_budget=0, epoch_steps=10, backend=be, clock=clock).run(jobs)
+    bounds = sorted({0.0} | {e[1] for e in be.log if e[0] == "epoch"})
+    for r in rep.results:
+        # admitted at the first epoch boundary at or after its arrival
+        nxt = min(b for b in bounds if b >= r.arrival - 1e-12) if r.arrival > 0 else 0.0
+        assert r.admitted >= r.arrival
+        assert r.admitted <= max(nxt, r.arrival) + 1e-9
+    resident = [e[2] for e in be.log if e[0] == "epoch"]
+    assert max(resident) >= 2                    # jobs overlapped on the device
+
+
+def test_a_diverging_job_is_reported_and_the_others_finish():
+    clock = SimClock()
+    be = FakeBackend(clock)
+    jobs = _jobs(5, seed=11)
+    bad = jobs[2]
+    bad.G, bad.tau, bad.steps = 40.0, 0.51, 40   # far past any stable coupling
+    rep = Server(hbm_budget=0, epoch_steps=8, backend=be, clock=clock).run(jobs)
+    by_id = {r.job_id: r for r in rep.results}
+    assert by_id[bad.job_id].status == "nonfinite"
+    assert all(r.status == "ok" for r in rep.results if r.job_id != bad.job_id)
+
+
+def test_offered_rate_scales_with_capacity():
+    jobs = _jobs(20)
+    r1 = offered_rate(jobs, capacity_mlups=1000.0, load=0.7)
+    r2 = offered_rate(jobs, capacity_mlups=2000.0, load=0.7)
+    assert abs(r2 / r1 - 2.0) < 1e-12
