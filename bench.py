@@ -125,19 +125,26 @@ def serve_leg(n_jobs: int, capacity_mlups: float, budget_gb: float, epoch: int):
     served with continuous batching, and sequentially (one job at a time, one
     lattice per launch) on the same arrivals."""
     import sc_inputs
+    from paper_1112_5547_amd import autotune
     from paper_1112_5547_amd.serve import GpuBackend, Server, offered_rate, sequential_baseline
     probe = sc_inputs.serving_jobs(n_jobs, seed=5, rate=1.0)
     rate = offered_rate(probe, capacity_mlups, load=0.7)
     jobs = sc_inputs.serving_jobs(n_jobs, seed=5, rate=rate)
-    rep = Server(hbm_budget=int(budget_gb * 1e9), epoch_steps=epoch, mode="persistent",
-                 backend=GpuBackend("fp32_shifted")).run(jobs)
+    # batch tiles for the job mix, timed on the 8 smallest jobs of each lattice type
+    sample = (sorted([j for j in jobs if j.lattice == 9], key=lambda j: j.sites)[:8]
+              + sorted([j for j in jobs if j.lattice == 19], key=lambda j: j.sites)[:8])
+    tiles = autotune.tune_batch(sample, precision="fp32_shifted", mode="fused", epoch=20)
+    rep = Server(hbm_budget=int(budget_gb * 1e9), epoch_steps=epoch, mode="fused",
+                 backend=GpuBackend("fp32_shifted"), tiles=tiles).run(jobs)
     served = rep.summary()
     seq = sequential_baseline(jobs, backend=GpuBackend("fp32_shifted"))
     r3 = lambda v: round(v, 3) if isinstance(v, float) else v
     return {"workload": f"{n_jobs} Poisson jobs (seed 5), 70% D2Q9 64^2-512^2 drops, 30% D3Q19 "
                         f"64^3-256^3 drops/spinodal, 500-5000 steps, FP32 shifted, "
                         f"offered load 0.7 x {capacity_mlups:.0f} MLUPS, budget {budget_gb:g} GB",
-            "arrival_rate_per_s": round(rate, 4),
+            "arrival_rate_per_s": round(rate, 4), "batch_tiles": tiles, "mode": "fused",
+            "nonfinite_jobs": [{"job": j.job_id, "tau": round(j.tau, 3), "G": round(j.G, 3)}
+                               for j in jobs if j.job_id in served["nonfinite_jobs"]],
             "served": {k: r3(v) for k, v in served.items()},
             "sequential": {k: r3(v) for k, v in seq.items()}}
 

@@ -77,6 +77,7 @@ class ServeReport:
             "max_queue": max((q for _, q, _ in self.queue_depth), default=0),
             "max_resident": max((r for _, _, r in self.queue_depth), default=0),
             "nonfinite": sum(r.status != "ok" for r in self.results),
+            "nonfinite_jobs": [r.job_id for r in self.results if r.status != "ok"],
             "refused": self.refused,
         }
 
@@ -134,7 +135,8 @@ class GpuBackend:
 class Server:
     def __init__(self, hbm_budget: int = 0, *, epoch_steps: int = 200, mode: str = "persistent",
                  max_resident: int = 256, backend=None, clock=None,
-                 keep_populations: bool = False, admit_hook: Optional[Callable] = None):
+                 keep_populations: bool = False, admit_hook: Optional[Callable] = None,
+                 tiles: Optional[dict] = None):
         self.budget = int(hbm_budget)
         self.epoch_steps = int(epoch_steps)
         self.mode = mode
@@ -143,6 +145,7 @@ class Server:
         self.clock = clock if clock is not None else WallClock()
         self.keep_populations = keep_populations
         self.admit_hook = admit_hook
+        self.tiles = tiles
 
     def run(self, jobs: Sequence) -> ServeReport:
         be, clock = self.backend, self.clock
@@ -154,6 +157,9 @@ class Server:
         depth: List[tuple] = []
         refused = 0
         batch = be.make_batch(self.budget)
+        if self.tiles:
+            batch.set_tiles(self.tiles["tx9"], self.tiles["tx19"], self.tiles["ty19"],
+                            self.tiles["mb9"], self.tiles["mb19"])
         epochs = 0
         need = {j.job_id: be.bytes_needed(j) for j in pending}
 
