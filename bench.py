@@ -31,6 +31,79 @@ WORKLOAD = ("D3Q19 two-component Shan-Chen BGK 256^3 periodic, spinodal from rho
             "+ U(-0.01,0.01) noise (seed 3), G=1.6, tau=1.0")
 
 
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1112_5547_amd", "csrc", f)
+                  for f in ("sc_device.h", "sc_kernels.hip")]
+COPY_BYTES = 2 << 30  # the copy-ceiling leg moves this many bytes each way per launch
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def record_traffic(fetch_csv: str, write_csv: str):
+    """Turns two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch) into per-launch HBM bytes of each step
+    kernel, scaled by what the same counters read for the copy kernel of
+    known size, and stores them with a hash of the kernel sources."""
+    import csv
+    import re
+
+    def per_kernel(path):
+        acc = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                k = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "").strip()
+                acc.setdefault(k, []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    F, W = per_kernel(fetch_csv), per_kernel(write_csv)
+    copy = [k for k in F if k.endswith("k_copy")][0]
+    fscale = COPY_BYTES / 1024.0 / F[copy]
+    wscale = COPY_BYTES / 1024.0 / W[copy]
+    out = {"sources_sha256": kernel_sources_sha(), "fetch_scale": fscale, "write_scale": wscale,
+           "kernels": {}}
+    for k in F:
+        if "k_step" in k:
+            out["kernels"][k] = {"fetch_kib": F[k], "write_kib": W.get(k),
+                                 "read_bytes": F[k] * 1024.0 * fscale,
+                                 "write_bytes": W.get(k, 0.0) * 1024.0 * wscale}
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1))
+
+
+def traffic_for(kernel_name: str, kernel_ms: float):
+    """Measured HBM GB/s of a step kernel from the committed counters, or None
+    if they are missing or were taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_JSON) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None, None
+    if t.get("sources_sha256") != kernel_sources_sha():
+        return None, None
+    e = t["kernels"].get(kernel_name)
+    if not e:
+        return None, None
+    b = e["read_bytes"] + e["write_bytes"]
+    return b / (kernel_ms * 1e-3) / 1e9, b
+
+
+def kernel_symbol(kern, precision: str) -> str:
+    variant, tx, ty, _ = kern
+    name = {0: "k_step_fused", 2: "k_step_pipe", 3: "k_step_repull"}.get(variant, "k_collide2")
+    pr = "sc::PF64" if precision == "fp64" else "sc::PF32S"
+    if variant == 1:
+        return f"sc::k_collide2<19, {pr}>"
+    return f"sc::{name}<19, {pr}, {tx}, {ty}>"
+
+
 def b_alg(q: int, esize: int) -> int:
     """Algorithmic bytes per site update: 2 species x Q x (read + write)."""
     return 2 * q * 2 * esize
@@ -163,7 +236,12 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=64)
     ap.add_argument("--kernel", type=str, default=None,
                     help="variant,tx,ty,mb of the FP64 step (default: tuned table)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="store per-launch HBM bytes from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(*args.record_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design, not a built path", file=sys.stderr)
@@ -181,6 +259,8 @@ def main():
     r64 = time_lattice(fields, "fp64", args.steps, args.warmup, kernel)
     mlups = n * args.steps / r64["wall_s"] / 1e6
     ach = b_alg(Q19, 8) * n / (r64["kernel_ms"] * 1e-3) / 1e9
+    sym64 = kernel_symbol(r64["kernel"], "fp64")
+    traffic64, tbytes64 = traffic_for(sym64, r64["kernel_ms"])
     out = {
         "metric": "MLUPS + % HBM roofline, D3Q19 2-comp SC 256^3; served-job p50/p99 latency",
         "value": round(mlups, 1),
@@ -197,8 +277,10 @@ def main():
         "config": {"workload": WORKLOAD, "lattice": "D3Q19", "size": [L, L, L],
                    "precision": "fp64", "kernel": list(r64["kernel"])},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBPS,
-                     "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBPS, 4), "traffic": None,
-                     "kernel": "k_step_fused<19,PF64>", "kernel_ms": round(r64["kernel_ms"], 4),
+                     "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBPS, 4),
+                     "traffic": None if traffic64 is None else round(traffic64, 1),
+                     "traffic_bytes_per_launch": tbytes64,
+                     "kernel": sym64, "kernel_ms": round(r64["kernel_ms"], 4),
                      "bytes_per_site": b_alg(Q19, 8)},
         "checks": {"mass_drift_A": (r64["T"]["mass_A"] - r64["T0"]["mass_A"]) / r64["T0"]["mass_A"],
                    "mom_x": r64["T"]["mom_x"], "max_u": r64["T"]["max_u"]},
@@ -206,11 +288,15 @@ def main():
     if not args.no_fp32:
         r32 = time_lattice(fields, "fp32_shifted", args.steps, args.warmup)
         ach32 = b_alg(Q19, 4) * n / (r32["kernel_ms"] * 1e-3) / 1e9
+        sym32 = kernel_symbol(r32["kernel"], "fp32_shifted")
+        traffic32, tbytes32 = traffic_for(sym32, r32["kernel_ms"])
         out["fp32_shifted"] = {
             "value": round(n * args.steps / r32["wall_s"] / 1e6, 1), "unit": "MLUPS",
             "ms_per_step": round(r32["wall_s"] * 1e3 / args.steps, 4),
             "roofline": {"bound": "hbm", "achieved": round(ach32, 1), "peak": PEAK_HBM_GBPS,
                          "unit": "GB/s", "frac": round(ach32 / PEAK_HBM_GBPS, 4),
+                         "traffic": None if traffic32 is None else round(traffic32, 1),
+                         "traffic_bytes_per_launch": tbytes32, "kernel": sym32,
                          "kernel_ms": round(r32["kernel_ms"], 4), "bytes_per_site": b_alg(Q19, 4)},
             "kernel": list(r32["kernel"]),
             "mass_drift_A": (r32["T"]["mass_A"] - r32["T0"]["mass_A"]) / r32["T0"]["mass_A"],
@@ -224,7 +310,7 @@ def main():
                                 "p99_latency_s": out["served"]["served"]["p99_latency_s"],
                                 "aggregate_mlups": out["served"]["served"]["aggregate_mlups"]}
     if not args.no_copy:
-        out["copy_ceiling_GBps"] = round(copy_bench(2 << 30, reps=10), 1)
+        out["copy_ceiling_GBps"] = round(copy_bench(COPY_BYTES, reps=10), 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(fields)
     print(json.dumps(out), flush=True)
