@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm_sc.so")
+# LBM_SC_LIB points the binding at another build of the same library (e.g. one
+# compiled with different tile tables); it must export the same symbols.
+LIB_PATH = os.environ.get("LBM_SC_LIB") or os.path.join(HERE, "liblbm_sc.so")
 
 LBM_D2Q9, LBM_D3Q19 = 9, 19
 LBM_FP64, LBM_FP32_SHIFTED = 0, 1

@@ -130,3 +130,22 @@ def test_laplace_law_linearity():
     assert r2 >= 0.999
     assert abs(b) <= 0.02 * dp.max()
     assert np.all(np.abs(np.array([r[1] for r in res]) - Rs) < 1.0)
+
+
+def test_kolmogorov_forcing_steady_state():
+    """Sec. 4.2 forcing F_x = rho A sin(2 pi y / L_y) with G = 0: the steady
+    flow solves nu u'' + A sin(ky) = 0, so u_phys = A / (nu k^2) sin(ky)."""
+    L, tau, A = 32, 1.0, 1e-6
+    shape = (1, L, 1)
+    f = oracle.init(9, np.full(shape, 0.5), np.full(shape, 0.5))
+    f = oracle.run(f, tau, tau, 0.0, 3000, body_A=A)
+    u = oracle.observables(f, tau, tau, 0.0, body_A=A)[1][0]
+    y = np.arange(L, dtype=float).reshape(1, L, 1)
+    k = 2 * np.pi / L
+    amp = _amplitude(u, k, y)
+    nu = CS2 * (tau - 0.5)
+    expect = A / (nu * k * k)
+    assert abs(amp - expect) / expect < 1e-2
+    # the component in phase with cos(ky) vanishes and the mean flow is zero
+    assert abs(2.0 * np.mean(u * np.cos(k * y))) < 1e-3 * expect
+    assert abs(u.mean()) < 1e-6 * expect
