@@ -534,8 +534,14 @@ struct TileStepPipe {
     static constexpr int FH = TY + 2 * HY;
     static constexpr int NT = TX * TY;
     static constexpr int R = Base::R;
-    static constexpr int RT = 2 * R;                        // ring (site, species) tasks
-    static constexpr int RPT = (RT + NT - 1) / NT;          // ring tasks per thread
+    // Ring (site, species) tasks are dealt out per wave so that a wave's
+    // species is uniform and its buffer resources stay scalar (a per-lane
+    // species would turn every ring load into a waterfall loop): wave task
+    // wt covers species wt & 1 of ring sites (wt >> 1) * 64 + lane.
+    static constexpr int NW = NT / 64;                      // waves per block
+    static constexpr int RW = (R + 63) / 64;                // waves per species
+    static constexpr int RPT = (2 * RW + NW - 1) / NW;      // ring tasks per thread
+    static_assert(NT % 64 == 0, "tiles hold whole waves");
     static constexpr int LDS_ELEMS = Base::LDS_ELEMS;
 
     __device__ static __forceinline__ int lidx(int slot, int s, int fy, int fx) {
@@ -613,16 +619,17 @@ struct TileStepPipe {
             for (int b = 0; b < 3; ++b)
                 off[a][b] = (uint32_t)(yy * NX + wrapi(gx + b - 1, NX)) * (uint32_t)sizeof(T);
         }
-        // ring tasks of this thread: task = tid + k*NT -> (site task/2, species task%2)
+        // ring tasks of this thread: wave task (tid / 64) + k * NW
         uint32_t roff[RPT][2 * HY + 1][3];
         int rfx[RPT], rfy[RPT], rsp[RPT];
         bool rok[RPT];
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int task = tid + k * NT;
-            rok[k] = task < RT;
-            const int site = rok[k] ? task >> 1 : 0;
-            rsp[k] = task & 1;
+            const int wt = (int)uni32((uint32_t)(tid >> 6)) + k * NW;
+            const int site0 = (wt >> 1) * 64 + (tid & 63);
+            rok[k] = wt < 2 * RW && site0 < R;
+            const int site = rok[k] ? site0 : 0;
+            rsp[k] = wt & 1;
             int lx, ly;
             ring_pos(site, lx, ly);
             rfx[k] = lx + 1;
@@ -754,8 +761,8 @@ struct TileStepRepull {
     static constexpr int FW = TX + 2;
     static constexpr int FH = TY + 2 * HY;
     static constexpr int NT = TX * TY;
-    static constexpr int RT = Pipe::RT;
     static constexpr int RPT = Pipe::RPT;
+    static constexpr int R = Pipe::R, NW = Pipe::NW, RW = Pipe::RW;
     static constexpr int LDS_ELEMS = Base::LDS_ELEMS;
 
     // density of one species from Q pulled loads, summed as they arrive
@@ -798,10 +805,11 @@ struct TileStepRepull {
         bool rok[RPT];
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int task = tid + k * NT;
-            rok[k] = task < RT;
-            const int site = rok[k] ? task >> 1 : 0;
-            rsp[k] = task & 1;
+            const int wt = (int)uni32((uint32_t)(tid >> 6)) + k * NW;
+            const int site0 = (wt >> 1) * 64 + (tid & 63);
+            rok[k] = wt < 2 * RW && site0 < R;
+            const int site = rok[k] ? site0 : 0;
+            rsp[k] = wt & 1;
             int lx, ly;
             Pipe::ring_pos(site, lx, ly);
             rfx[k] = lx + 1;
