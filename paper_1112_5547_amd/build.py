@@ -22,6 +22,9 @@ ARCH = os.environ.get("LBM_SC_ARCH", "gfx950")
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+    # no implicit contraction: the device code writes its fused multiply-adds
+    # out, so every kernel variant rounds identically
+    "-ffp-contract=off",
     # packed FP32 instructions stay off: plain scalar FP32 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -236,6 +236,36 @@ __device__ __forceinline__ double kolmogorov(const StepParams& p, int y) {
     return p.body_A * sin(2.0 * M_PI * (double)y / (double)p.ny_lat);
 }
 
+// Floating-point contraction.  The library is compiled without implicit
+// contraction; the fused multiply-adds below are written out, so every launch
+// form performs the same IEEE operations in the same order and a lattice
+// evolves bitwise the same whichever kernel variant, tile shape or batch
+// advances it.
+__device__ __forceinline__ double fmaa(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaa(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Force gather of both species, g[s] = sum_{i>0} w_i rho_s(x + c_i) c_i (the
+// sum of eq. FORCE without the -G psi_s' factor); rho(s, i) returns the
+// density of species s at the neighbour x + c_i.
+template <int Q, class A, class Rho>
+__device__ __forceinline__ void gather(Rho&& rho, A (&g)[2][3]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        A gx = A(0), gy = A(0), gz = A(0);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const A r = rho(s, i);
+            const A w = A(VSet<Q>::w(i));
+            if (VSet<Q>::cx(i)) gx = fmaa(VSet<Q>::cx(i) > 0 ? w : -w, r, gx);
+            if (VSet<Q>::cy(i)) gy = fmaa(VSet<Q>::cy(i) > 0 ? w : -w, r, gy);
+            if (VSet<Q>::cz(i)) gz = fmaa(VSet<Q>::cz(i) > 0 ? w : -w, r, gz);
+        }
+        g[s][0] = gx;
+        g[s][1] = gy;
+        g[s][2] = gz;
+    }
+}
+
 // Collision of one site and store of its 2Q post-collision populations.
 //   f      : the site's pulled populations f_is(x, t) (shifted h_is in FP32 mode)
 //   g[s]   : sum_i w_i rho_s(x + c_i) c_i, the gather of species s
@@ -274,20 +304,20 @@ __device__ __forceinline__ void collide_store(const typename PR::T (&f)[2][Q],
         j[s][2] = jz;
     }
     // common velocity weighted by 1/tau_s, then the force shift of each species
-    const A den = rfull[0] * om[0] + rfull[1] * om[1];
+    const A den = fmaa(rfull[0], om[0], rfull[1] * om[1]);
     A u[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = (j[0][a] * om[0] + j[1][a] * om[1]) / den;
+    for (int a = 0; a < 3; ++a) u[a] = fmaa(j[0][a], om[0], j[1][a] * om[1]) / den;
     const A bx = A(body);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const int so = 1 - s;
         A v[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) v[a] = u[a] + tau[s] * (-G * g[so][a]);
-        v[0] += tau[s] * bx;
-        const A vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-        const A base = A(1) - A(1.5) * vv;
+        for (int a = 0; a < 3; ++a) v[a] = fmaa(tau[s], -G * g[so][a], u[a]);
+        v[0] = fmaa(tau[s], bx, v[0]);
+        const A vv = fmaa(v[0], v[0], fmaa(v[1], v[1], v[2] * v[2]));
+        const A base = fmaa(A(-1.5), vv, A(1));
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             A cu = A(0);
@@ -298,13 +328,13 @@ __device__ __forceinline__ void collide_store(const typename PR::T (&f)[2][Q],
             A feq;
             if (PR::shifted) {
                 // h^eq = f^eq - w rho_ref = w [delta + rho (3cu + 4.5cu^2 - 1.5vv)]
-                const A poly = A(3) * cu + A(4.5) * cu * cu - A(1.5) * vv;
-                feq = wi * (rho[s] + rfull[s] * poly);
+                const A poly = fmaa(A(4.5) * cu, cu, fmaa(A(3), cu, A(-1.5) * vv));
+                feq = wi * fmaa(rfull[s], poly, rho[s]);
             } else {
-                feq = wi * rfull[s] * (base + A(3) * cu + A(4.5) * cu * cu);
+                feq = wi * rfull[s] * fmaa(A(4.5) * cu, cu, fmaa(A(3), cu, base));
             }
             const A fv = A(f[s][i]);
-            const A fo = fv + om[s] * (feq - fv);
+            const A fo = fmaa(om[s], feq - fv, fv);
             buf_store_nt<T>(T(fo), make_rsrc(dst + (size_t)(s * Q + i) * pbytes, pbytes), voff,
                             soff);
         }
@@ -486,23 +516,10 @@ struct TileStep {
             if (valid) {
                 // force gather from the LDS density planes m-1, m, m+1
                 A g[2][3];
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    A gx_ = A(0), gy_ = A(0), gz_ = A(0);
-#pragma unroll
-                    for (int i = 1; i < Q; ++i) {
-                        const int slot = (k + 1 + Geo<Q>::dm(i)) & 3;
-                        const A r = lds[lidx(slot, s, own_fy + Geo<Q>::dy(i),
-                                              own_fx + Geo<Q>::dx(i))];
-                        const A wr = A(VSet<Q>::w(i)) * r;
-                        if (VSet<Q>::cx(i)) gx_ += VSet<Q>::cx(i) > 0 ? wr : -wr;
-                        if (VSet<Q>::cy(i)) gy_ += VSet<Q>::cy(i) > 0 ? wr : -wr;
-                        if (VSet<Q>::cz(i)) gz_ += VSet<Q>::cz(i) > 0 ? wr : -wr;
-                    }
-                    g[s][0] = gx_;
-                    g[s][1] = gy_;
-                    g[s][2] = gz_;
-                }
+                gather<Q>([&](int s, int i) {
+                    const int slot = (k + 1 + Geo<Q>::dm(i)) & 3;
+                    return lds[lidx(slot, s, own_fy + Geo<Q>::dy(i), own_fx + Geo<Q>::dx(i))];
+                }, g);
                 const double body = p.body_A != 0.0 ? kolmogorov(p, HY ? gy : m) : 0.0;
                 collide_store<Q, PR>(cur, g, p, body, dst, pbytes, own_voff,
                                      __builtin_amdgcn_readfirstlane((uint32_t)m * P *
@@ -700,23 +717,10 @@ struct TileStepPipe {
             if (valid) {
                 const int km = slot_of(m);
                 A g[2][3];
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    A gx_ = A(0), gy_ = A(0), gz_ = A(0);
-#pragma unroll
-                    for (int i = 1; i < Q; ++i) {
-                        const int slot = (km + Geo<Q>::dm(i)) & 3;
-                        const A r = lds[lidx(slot, s, own_fy + Geo<Q>::dy(i),
-                                              own_fx + Geo<Q>::dx(i))];
-                        const A wr = A(VSet<Q>::w(i)) * r;
-                        if (VSet<Q>::cx(i)) gx_ += VSet<Q>::cx(i) > 0 ? wr : -wr;
-                        if (VSet<Q>::cy(i)) gy_ += VSet<Q>::cy(i) > 0 ? wr : -wr;
-                        if (VSet<Q>::cz(i)) gz_ += VSet<Q>::cz(i) > 0 ? wr : -wr;
-                    }
-                    g[s][0] = gx_;
-                    g[s][1] = gy_;
-                    g[s][2] = gz_;
-                }
+                gather<Q>([&](int s, int i) {
+                    const int slot = (km + Geo<Q>::dm(i)) & 3;
+                    return lds[lidx(slot, s, own_fy + Geo<Q>::dy(i), own_fx + Geo<Q>::dx(i))];
+                }, g);
                 const double body = p.body_A != 0.0 ? kolmogorov(p, HY ? gy : m) : 0.0;
                 collide_store<Q, PR>(r0, g, p, body, dst, pbytes, own_voff,
                                      __builtin_amdgcn_readfirstlane((uint32_t)m * P *
@@ -860,23 +864,10 @@ struct TileStepRepull {
             if (valid) {
                 const int km = slot_of(m);
                 A g[2][3];
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    A gx_ = A(0), gy_ = A(0), gz_ = A(0);
-#pragma unroll
-                    for (int i = 1; i < Q; ++i) {
-                        const int slot = (km + Geo<Q>::dm(i)) & 3;
-                        const A r = lds[Base::lidx(slot, s, own_fy + Geo<Q>::dy(i),
-                                                    own_fx + Geo<Q>::dx(i))];
-                        const A wr = A(VSet<Q>::w(i)) * r;
-                        if (VSet<Q>::cx(i)) gx_ += VSet<Q>::cx(i) > 0 ? wr : -wr;
-                        if (VSet<Q>::cy(i)) gy_ += VSet<Q>::cy(i) > 0 ? wr : -wr;
-                        if (VSet<Q>::cz(i)) gz_ += VSet<Q>::cz(i) > 0 ? wr : -wr;
-                    }
-                    g[s][0] = gx_;
-                    g[s][1] = gy_;
-                    g[s][2] = gz_;
-                }
+                gather<Q>([&](int s, int i) {
+                    const int slot = (km + Geo<Q>::dm(i)) & 3;
+                    return lds[Base::lidx(slot, s, own_fy + Geo<Q>::dy(i), own_fx + Geo<Q>::dx(i))];
+                }, g);
                 const double body = p.body_A != 0.0 ? kolmogorov(p, HY ? gy : m) : 0.0;
                 collide_store<Q, PR>(cur, g, p, body, dst, pbytes, own_voff,
                                      __builtin_amdgcn_readfirstlane((uint32_t)m * P *

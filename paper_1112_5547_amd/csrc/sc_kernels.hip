@@ -269,22 +269,10 @@ __global__ void __launch_bounds__(256) k_collide2(StepParams p, const typename P
             v[s][i] = f[(size_t)(s * Q + i) * p.N +
                         site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)];
     A gs[2][3];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        A gx = A(0), gy = A(0), gz = A(0);
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const A r = psi[(size_t)s * p.N +
-                            site_at(g, VSet<Q>::cx(i), VSet<Q>::cy(i), VSet<Q>::cz(i), nx, ny, nz)];
-            const A wr = A(VSet<Q>::w(i)) * r;
-            if (VSet<Q>::cx(i)) gx += VSet<Q>::cx(i) > 0 ? wr : -wr;
-            if (VSet<Q>::cy(i)) gy += VSet<Q>::cy(i) > 0 ? wr : -wr;
-            if (VSet<Q>::cz(i)) gz += VSet<Q>::cz(i) > 0 ? wr : -wr;
-        }
-        gs[s][0] = gx;
-        gs[s][1] = gy;
-        gs[s][2] = gz;
-    }
+    gather<Q>([&](int s, int i) {
+        return psi[(size_t)s * p.N +
+                   site_at(g, VSet<Q>::cx(i), VSet<Q>::cy(i), VSet<Q>::cz(i), nx, ny, nz)];
+    }, gs);
     const double body = p.body_A != 0.0 ? kolmogorov(p, g.y) : 0.0;
     collide_store<Q, PR>(v, gs, p, body, static_cast<char*>(p.dst), p.N * (uint32_t)sizeof(T),
                          site * (uint32_t)sizeof(T), 0u);
