@@ -191,31 +191,40 @@ def batch_leg(n_jobs: int, steps: int, epoch: int):
     return out
 
 
-def serve_leg(n_jobs: int, capacity_mlups: float, budget_gb: float, epoch: int):
+def serve_leg(n_jobs: int, budget_gb: float, epoch: int):
     """Poisson stream of drop / spinodal jobs (seed 5): 70 % D2Q9 drops
     L~U{64..512}, 30 % D3Q19 L~U{64..256} (half drops, half spinodal), steps
-    U{500..5000}, FP32 shifted; offered load 0.7 x the measured FP32 capacity;
-    served with continuous batching, and sequentially (one job at a time, one
-    lattice per launch) on the same arrivals."""
+    U{500..5000}, FP32 shifted.  The arrival rate offers 0.7 x the capacity of
+    one-job-at-a-time service for this job mix (solo step times measured per
+    lattice shape).  Served with continuous batching (shortest remaining work
+    first), and sequentially (one job at a time, one lattice per launch) on the
+    same arrivals."""
     import sc_inputs
     from paper_1112_5547_amd import autotune
-    from paper_1112_5547_amd.serve import GpuBackend, Server, offered_rate, sequential_baseline
+    from paper_1112_5547_amd.serve import (GpuBackend, Server, offered_rate, sequential_baseline,
+                                           solo_capacity, solo_step_seconds)
     probe = sc_inputs.serving_jobs(n_jobs, seed=5, rate=1.0)
-    rate = offered_rate(probe, capacity_mlups, load=0.7)
+    step_s = solo_step_seconds(probe, GpuBackend("fp32_shifted"))
+    capacity = solo_capacity(probe, step_s)
+    rate = offered_rate(probe, capacity, load=0.7)
     jobs = sc_inputs.serving_jobs(n_jobs, seed=5, rate=rate)
     # batch tiles for the job mix, timed on the 8 smallest jobs of each lattice type
     sample = (sorted([j for j in jobs if j.lattice == 9], key=lambda j: j.sites)[:8]
               + sorted([j for j in jobs if j.lattice == 19], key=lambda j: j.sites)[:8])
     tiles = autotune.tune_batch(sample, precision="fp32_shifted", mode="fused", epoch=20)
-    rep = Server(hbm_budget=int(budget_gb * 1e9), epoch_steps=epoch, mode="fused",
-                 backend=GpuBackend("fp32_shifted"), tiles=tiles).run(jobs)
+    server = Server(hbm_budget=int(budget_gb * 1e9), epoch_steps=epoch, mode="fused",
+                    backend=GpuBackend("fp32_shifted"), tiles=tiles, policy="srpt")
+    rep = server.run(jobs)
     served = rep.summary()
     seq = sequential_baseline(jobs, backend=GpuBackend("fp32_shifted"))
     r3 = lambda v: round(v, 3) if isinstance(v, float) else v
     return {"workload": f"{n_jobs} Poisson jobs (seed 5), 70% D2Q9 64^2-512^2 drops, 30% D3Q19 "
-                        f"64^3-256^3 drops/spinodal, 500-5000 steps, FP32 shifted, "
-                        f"offered load 0.7 x {capacity_mlups:.0f} MLUPS, budget {budget_gb:g} GB",
-            "arrival_rate_per_s": round(rate, 4), "batch_tiles": tiles, "mode": "fused",
+                        f"64^3-256^3 drops/spinodal, 500-5000 steps, FP32 shifted, offered load "
+                        f"0.7 x {capacity:.0f} MLUPS (solo service of this mix), budget "
+                        f"{budget_gb:g} GB",
+            "arrival_rate_per_s": round(rate, 4), "solo_capacity_mlups": round(capacity, 1),
+            "batch_tiles": tiles, "mode": "fused", "policy": server.policy,
+            "sat_sites": server.sat_sites, "epoch_steps": epoch,
             "nonfinite_jobs": [{"job": j.job_id, "tau": round(j.tau, 3), "G": round(j.G, 3)}
                                for j in jobs if j.job_id in served["nonfinite_jobs"]],
             "served": {k: r3(v) for k, v in served.items()},
@@ -233,7 +242,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-lattices leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-jobs leg")
     ap.add_argument("--batch-steps", type=int, default=2000)
-    ap.add_argument("--serve-jobs", type=int, default=64)
+    ap.add_argument("--serve-jobs", type=int, default=48)
     ap.add_argument("--kernel", type=str, default=None,
                     help="variant,tx,ty,mb of the FP64 step (default: tuned table)")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -304,8 +313,7 @@ def main():
     if not args.no_batch:
         out["batched"] = batch_leg(64, args.batch_steps, epoch=250)
     if not args.no_serve:
-        cap = out.get("fp32_shifted", {}).get("value", 10000.0)
-        out["served"] = serve_leg(args.serve_jobs, cap, budget_gb=96.0, epoch=250)
+        out["served"] = serve_leg(args.serve_jobs, budget_gb=96.0, epoch=250)
         out["metric_served"] = {"p50_latency_s": out["served"]["served"]["p50_latency_s"],
                                 "p99_latency_s": out["served"]["served"]["p99_latency_s"],
                                 "aggregate_mlups": out["served"]["served"]["aggregate_mlups"]}

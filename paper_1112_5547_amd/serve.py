@@ -6,8 +6,19 @@ counts) arrive over time.  The loop:
 * queues every request whose arrival time has passed;
 * admits queued jobs first-fit while the device-memory budget and the member
   slots allow (a job's state stays resident on the device until it finishes);
-* advances all resident jobs together in epochs of ``epoch_steps`` steps with
-  one batch launch per epoch (persistent, fused or per-lattice form);
+* advances resident jobs in epochs of ``epoch_steps`` steps with one batch
+  launch per epoch (persistent, fused or per-lattice form).  Which resident
+  jobs an epoch advances is the scheduling policy:
+    - ``"srpt"`` (default): shortest remaining work first.  Resident jobs are
+      ordered by remaining site updates and taken until their lattices hold
+      ``sat_sites`` sites, the size at which one batch launch keeps the whole
+      device busy; the rest wait, resident, for a later epoch.  A small job
+      then never pays the step time of a large one, and a large job still runs
+      at full rate once it is the shortest.  An epoch whose only member fills
+      the device by itself (at least ``sat_sites`` sites) steps that lattice
+      alone with its own tuned kernel instead of the batch launch;
+    - ``"all"``: every resident job advances every epoch (each job gets the
+      same number of steps per epoch, whatever its size);
 * while an epoch runs on the device, prepares the next admissions on the host
   (input fields, lattice creation, upload); jobs that arrive mid-epoch join at
   the next epoch boundary;
@@ -136,7 +147,12 @@ class Server:
     def __init__(self, hbm_budget: int = 0, *, epoch_steps: int = 200, mode: str = "persistent",
                  max_resident: int = 256, backend=None, clock=None,
                  keep_populations: bool = False, admit_hook: Optional[Callable] = None,
-                 tiles: Optional[dict] = None):
+                 tiles: Optional[dict] = None, policy: str = "srpt",
+                 sat_sites: int = 4_000_000):
+        if policy not in ("srpt", "all"):
+            raise ValueError(f"unknown scheduling policy {policy!r}")
+        self.policy = policy
+        self.sat_sites = int(sat_sites)
         self.budget = int(hbm_budget)
         self.epoch_steps = int(epoch_steps)
         self.mode = mode
@@ -149,14 +165,19 @@ class Server:
 
     def run(self, jobs: Sequence) -> ServeReport:
         be, clock = self.backend, self.clock
+        srpt = self.policy == "srpt"
         pending = sorted(jobs, key=lambda j: j.arrival)
         queue: List = []
         resident: Dict[int, tuple] = {}       # job_id -> (job, lattice, admitted_at)
+        done_steps: Dict[int, int] = {}       # job_id -> steps advanced so far
+        active: set = set()                   # job_ids that are members of the batch
         used = 0
         results: List[JobResult] = []
         depth: List[tuple] = []
         refused = 0
-        batch = be.make_batch(self.budget)
+        # the server accounts the memory of every resident job; under SRPT the
+        # batch only holds the jobs of the current epoch
+        batch = be.make_batch(0 if srpt else self.budget)
         if self.tiles:
             batch.set_tiles(self.tiles["tx9"], self.tiles["tx19"], self.tiles["ty19"],
                             self.tiles["mb9"], self.tiles["mb19"])
@@ -178,18 +199,49 @@ class Server:
                 fits = not self.budget or used + need[job.job_id] <= self.budget
                 if len(resident) < self.max_resident and fits:
                     lat = be.make_lattice(job)
-                    if not batch.add(lat, job.steps):
-                        be.release(lat)
-                        k += 1
-                        continue
+                    if not srpt:
+                        if not batch.add(lat, job.steps):
+                            be.release(lat)
+                            k += 1
+                            continue
+                        active.add(job.job_id)
                     used += need[job.job_id]
                     resident[job.job_id] = (job, lat, clock.now())
+                    done_steps[job.job_id] = 0
                     queue.pop(k)
                     if self.admit_hook:
                         self.admit_hook(job, clock.now())
                 else:
                     k += 1
             depth.append((clock.now(), len(queue), len(resident)))
+
+        def remaining(jid: int) -> int:
+            return resident[jid][0].steps - done_steps[jid]
+
+        def schedule() -> Optional[int]:
+            """SRPT: the next epoch's members are the resident jobs with the
+            least remaining work, taken until their sites reach sat_sites.
+            Returns the job to step alone when it is the only member and fills
+            the device by itself, else None (the batch runs the epoch)."""
+            if not srpt:
+                return None
+            order = sorted(resident, key=lambda j: (remaining(j) * resident[j][0].sites,
+                                                    resident[j][0].arrival, j))
+            chosen, sites = [], 0
+            for jid in order:
+                if chosen and sites >= self.sat_sites:
+                    break
+                chosen.append(jid)
+                sites += resident[jid][0].sites
+            solo = chosen[0] if len(chosen) == 1 and sites >= self.sat_sites else None
+            keep = set() if solo is not None else set(chosen)
+            for jid in sorted(active - keep):
+                batch.remove(resident[jid][1])
+                active.discard(jid)
+            for jid in sorted(keep - active):
+                batch.add(resident[jid][1], remaining(jid))
+                active.add(jid)
+            return solo
 
         admit()
         while pending or queue or resident:
@@ -206,15 +258,30 @@ class Server:
                 clock.sleep_until(pending[0].arrival)
                 admit()
                 continue
-            batch.run(self.epoch_steps, self.mode)   # asynchronous on the device
-            epochs += 1
-            admit()                                    # host work overlaps the epoch
-            done = batch.poll()                        # waits for the epoch
+            solo = schedule()
+            if solo is not None:
+                lat = resident[solo][1]
+                lat.step(min(self.epoch_steps, remaining(solo)))   # its own stream and kernel
+                epochs += 1
+                done_steps[solo] += min(self.epoch_steps, remaining(solo))
+                admit()                                    # host work overlaps the epoch
+                lat.sync()
+                done = [lat] if remaining(solo) == 0 else []
+            else:
+                batch.run(self.epoch_steps, self.mode)   # asynchronous on the device
+                epochs += 1
+                for jid in active:
+                    done_steps[jid] += min(self.epoch_steps, remaining(jid))
+                admit()                                    # host work overlaps the epoch
+                done = batch.poll()                        # waits for the epoch
             t_done = clock.now()
             for lat in done:
                 jid = next(j for j, (_, l, _) in resident.items() if l is lat)
                 job, _, t_adm = resident.pop(jid)
-                batch.remove(lat)
+                if jid in active:
+                    batch.remove(lat)
+                    active.discard(jid)
+                done_steps.pop(jid)
                 T, pops = be.finish(lat, self.keep_populations)
                 status = "ok" if T.get("n_nonfinite", 0) == 0 else "nonfinite"
                 results.append(JobResult(job.job_id, job.lattice, (job.nz, job.ny, job.nx),
@@ -228,6 +295,32 @@ class Server:
             batch.close()
         results.sort(key=lambda r: r.job_id)
         return ServeReport(results, makespan, epochs, depth, refused)
+
+
+def solo_step_seconds(jobs, backend=None, *, warm: int = 32, timed: int = 64) -> Dict[tuple, float]:
+    """Seconds per step of each distinct lattice shape of `jobs` run alone
+    (one lattice per launch, the backend's tuned kernel), timed on the device
+    after `warm` steps (which include any graph capture).  Keys are
+    (lattice, nx, ny, nz)."""
+    be = backend if backend is not None else GpuBackend()
+    out: Dict[tuple, float] = {}
+    for job in jobs:
+        key = (job.lattice, job.nx, job.ny, job.nz)
+        if key in out:
+            continue
+        lat = be.make_lattice(job)
+        lat.step(warm)
+        out[key] = lat.time_steps(timed) * 1e-3 / timed
+        be.release(lat)
+    return out
+
+
+def solo_capacity(jobs, step_seconds: Dict[tuple, float]) -> float:
+    """Site updates per second (in millions) of the job mix served one job at
+    a time: total work over the sum of the jobs' solo service times."""
+    work = sum(j.sites * j.steps for j in jobs)
+    busy = sum(j.steps * step_seconds[(j.lattice, j.nx, j.ny, j.nz)] for j in jobs)
+    return work / busy / 1e6
 
 
 def offered_rate(jobs, capacity_mlups: float, load: float = 0.7) -> float:
@@ -255,4 +348,5 @@ def sequential_baseline(jobs, backend=None, clock=None) -> dict:
     t = clock.now()
     return {"p50_latency_s": float(np.percentile(lat_s, 50)),
             "p99_latency_s": float(np.percentile(lat_s, 99)),
+            "mean_latency_s": float(np.mean(lat_s)),
             "makespan_s": t, "aggregate_mlups": su / t / 1e6}

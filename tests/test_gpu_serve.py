@@ -15,16 +15,21 @@ def _jobs(n, seed, rate):
                                   l3=(16, 40), frac_3d=0.35)
 
 
-@pytest.mark.parametrize("precision,mode", [("fp32_shifted", "persistent"), ("fp64", "fused")])
-def test_served_results_equal_solo_runs(precision, mode):
+@pytest.mark.parametrize("precision,mode,policy,sat", [
+    ("fp32_shifted", "persistent", "srpt", 4_000_000),
+    ("fp64", "fused", "srpt", 4_000_000),
+    ("fp32_shifted", "fused", "srpt", 20_000),     # lone large jobs step by themselves
+    ("fp64", "persistent", "all", 4_000_000),
+])
+def test_served_results_equal_solo_runs(precision, mode, policy, sat):
     from paper_1112_5547_amd import Lattice
     from paper_1112_5547_amd.serve import GpuBackend, Server
     jobs = _jobs(14, seed=31, rate=400.0)
     be = GpuBackend(precision=precision)
     budget = sum(sorted(be.bytes_needed(j) for j in jobs)[-4:])  # forces queueing
-    say(f"serve 14 jobs {precision} {mode}, budget {budget}")
+    say(f"serve 14 jobs {precision} {mode} {policy} sat {sat}, budget {budget}")
     rep = Server(hbm_budget=budget, epoch_steps=64, mode=mode, backend=be,
-                 keep_populations=True).run(jobs)
+                 keep_populations=True, policy=policy, sat_sites=sat).run(jobs)
     s = rep.summary()
     assert s["jobs"] == len(jobs) and s["nonfinite"] == 0 and s["refused"] == 0
     assert s["max_resident"] >= 2

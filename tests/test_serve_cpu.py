@@ -1,6 +1,7 @@
 """Serving-loop logic on the CPU: an oracle-driven backend and a simulated
 clock stand in for the GPU library, so admission by memory budget, epochs,
-joins between epochs, read-out, refusal and latency accounting are tested
+joins between epochs, scheduling (shortest remaining work first, or every
+resident job each epoch), read-out, refusal and latency accounting are tested
 without a device.  Results must equal each job's solo oracle run bitwise
 (the backend advances every member with the same oracle code)."""
 import numpy as np
@@ -26,8 +27,9 @@ class SimClock:
 
 
 class FakeLattice:
-    def __init__(self, job):
+    def __init__(self, job, backend):
         self.job = job
+        self.be = backend
         self.q = job.lattice
         self.shape = (job.nz, job.ny, job.nx)
         fl = job.fields()
@@ -38,6 +40,15 @@ class FakeLattice:
         if n > 0:
             self.f = oracle.run(self.f, self.job.tau, self.job.tau, self.job.G, n)
             self.steps_done += n
+
+    def step(self, n):
+        """A solo launch: same oracle arithmetic, the clock moves by its work."""
+        self.advance(n)
+        self.be.clock.advance(n * np.prod(self.shape) / self.be.capacity + 1e-4)
+        self.be.log.append(("solo", self.job.job_id, n))
+
+    def sync(self):
+        pass
 
 
 class FakeBatch:
@@ -72,6 +83,7 @@ class FakeBatch:
             work += k * np.prod(m[0].shape)
         self.clock.advance(work / self.capacity + 1e-4)
         self.log.append(("epoch", self.clock.now(), len(self.members)))
+        self.log.append(("members", [m[0].job.job_id for m in self.members.values()]))
 
     def poll(self):
         return [m[0] for m in self.members.values() if m[1] == 0]
@@ -85,7 +97,7 @@ class FakeBackend:
         return 2 * 2 * job.lattice * job.sites * 4       # FP32 ping-pong populations
 
     def make_lattice(self, job):
-        return FakeLattice(job)
+        return FakeLattice(job, self)
 
     def make_batch(self, budget):
         return FakeBatch(budget, self.clock, self.capacity, self.bytes_needed, self.log)
@@ -178,3 +190,93 @@ def test_offered_rate_scales_with_capacity():
     r1 = offered_rate(jobs, capacity_mlups=1000.0, load=0.7)
     r2 = offered_rate(jobs, capacity_mlups=2000.0, load=0.7)
     assert abs(r2 / r1 - 2.0) < 1e-12
+
+
+def _job(jid, L, steps, arrival, q=9):
+    nz = L if q == 19 else 1
+    return sc_inputs.JobSpec(jid, q, L, L, nz, 1.0, 1.3, steps, "drop", L / 5.0, seed=jid,
+                             arrival=arrival)
+
+
+def test_srpt_lets_a_short_job_overtake_a_long_one():
+    """A long job is running when a short one arrives: shortest remaining work
+    first finishes the short one first; advancing every resident job each
+    epoch makes it wait for the long job's step time, and it completes later."""
+    done_at = {}
+    for policy in ("srpt", "all"):
+        clock = SimClock()
+        be = FakeBackend(clock, capacity=2e4)
+        jobs = [_job(0, 24, 200, 0.0), _job(1, 8, 20, 0.05)]
+        rep = Server(hbm_budget=0, epoch_steps=10, backend=be, clock=clock, policy=policy,
+                     sat_sites=64).run(jobs)
+        by_id = {r.job_id: r for r in rep.results}
+        done_at[policy] = (by_id[0].completed, by_id[1].completed)
+    assert done_at["srpt"][1] < done_at["srpt"][0]
+    assert done_at["srpt"][1] < done_at["all"][1]
+
+
+def test_srpt_epochs_hold_at_most_the_saturating_prefix():
+    """Every epoch's members are a shortest-remaining-work prefix that stops
+    once sat_sites is reached: dropping its largest lattice leaves fewer
+    sites than sat_sites."""
+    clock = SimClock()
+    be = FakeBackend(clock)
+    jobs = _jobs(12, seed=7, rate=1000.0)
+    sat = 600
+    Server(hbm_budget=0, epoch_steps=6, backend=be, clock=clock, sat_sites=sat).run(jobs)
+    sites = {j.job_id: j.sites for j in jobs}
+    epochs = [e[1] for e in be.log if e[0] == "members"]
+    assert epochs and max(len(m) for m in epochs) >= 2
+    for members in epochs:
+        tot = sum(sites[j] for j in members)
+        assert len(members) == 1 or tot - max(sites[j] for j in members) < sat
+
+
+def test_both_policies_give_each_job_its_solo_result():
+    res = {}
+    for policy in ("srpt", "all"):
+        clock = SimClock()
+        be = FakeBackend(clock)
+        jobs = _jobs(8, seed=13, rate=300.0)
+        rep = Server(hbm_budget=0, epoch_steps=7, backend=be, clock=clock, policy=policy,
+                     sat_sites=300, keep_populations=True).run(jobs)
+        res[policy] = {r.job_id: r.populations for r in rep.results}
+    assert res["srpt"].keys() == res["all"].keys()
+    for k in res["srpt"]:
+        assert np.array_equal(res["srpt"][k], res["all"][k])
+
+
+def test_unknown_policy_is_rejected():
+    with pytest.raises(ValueError):
+        Server(policy="fifo")
+
+
+def test_solo_capacity_is_work_over_summed_service_time():
+    from paper_1112_5547_amd.serve import solo_capacity
+    jobs = [_job(0, 10, 100, 0.0), _job(1, 20, 50, 0.0), _job(2, 10, 300, 0.0)]
+    step_s = {(9, 10, 10, 1): 1e-5, (9, 20, 20, 1): 4e-5}
+    work = 100 * 100 + 400 * 50 + 100 * 300
+    busy = 100 * 1e-5 + 50 * 4e-5 + 300 * 1e-5
+    assert abs(solo_capacity(jobs, step_s) - work / busy / 1e6) < 1e-12
+
+
+def test_srpt_steps_a_saturating_lone_job_by_itself():
+    """A job whose lattice alone reaches sat_sites runs solo launches when it
+    is the only member of an epoch; its result is still its solo result.  The
+    two small jobs and the big one form the saturating prefix for two epochs
+    (16 of the big job's steps in the batch); the other 14 run alone."""
+    clock = SimClock()
+    be = FakeBackend(clock)
+    jobs = [_job(0, 20, 30, 0.0), _job(1, 6, 12, 0.0), _job(2, 7, 9, 0.0)]
+    rep = Server(hbm_budget=0, epoch_steps=8, backend=be, clock=clock, sat_sites=400,
+                 keep_populations=True).run(jobs)
+    solo = [e for e in be.log if e[0] == "solo"]
+    assert solo and all(e[1] == 0 for e in solo)
+    assert sum(e[2] for e in solo) == 30 - 16
+    by_id = {r.job_id: r for r in rep.results}
+    assert by_id[1].completed < by_id[0].completed and by_id[2].completed < by_id[0].completed
+    for job in jobs:
+        fl = job.fields()
+        ref = oracle.run(oracle.init(job.lattice, fl.rho_A, fl.rho_B), job.tau, job.tau, job.G,
+                         job.steps)
+        assert np.array_equal(by_id[job.job_id].populations, ref)
