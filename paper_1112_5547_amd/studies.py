@@ -8,6 +8,13 @@
   amplified, so the comparison is statistical.
 * ``drop_study``: a static drop; per-species mass, spurious max |u_phys|,
   Laplace pressure Delta p and R_eff in both precisions.
+* ``paper_drop_kolmogorov``: the paper's own two-phase test (Sec. 4): a D2Q9
+  drop on a periodic 100 x 100 grid with tau = 0.55, rho = 1.4, g_AB = 0.164
+  and R = L/4 is run to a steady state (Sec. 4.1: surface tension
+  sigma(t) = R [P_i - P_o], spurious currents, bulk order parameter), then
+  the Kolmogorov force F_x = rho A sin(2 pi y / L_y), A = 1e-6, is switched on
+  (Sec. 4.2: total kinetic energy and the leakage L(t) = M(t) / M_0, M the
+  number of nodes with phi >= 0) until the flow is steady again.
 
 Fields are copied to the host only at the checkpoints; S(k) is evaluated
 there with numpy.fft (a diagnostic, not part of the step).
@@ -85,6 +92,60 @@ def drop_study(L: int = 128, steps: int = 1000, *, R: float = 24.0, G: float = 1
     return out
 
 
+def paper_drop_kolmogorov(precision: str = "fp64", *, L: int = 100, steps_static: int = 40000,
+                          steps_forced: int = 80000, every: int = 1000, A: float = 1e-6,
+                          tau: float = 0.55, rho: float = 1.4, G: float = 0.164) -> dict:
+    """The paper's static drop and its deformation under Kolmogorov flow.
+
+    The drop starts as a tanh profile of phi = +-1 (rho_A = (rho + phi) / 2),
+    at rest, radius L/4.  The forced phase continues from the settled state:
+    its populations are moved to a lattice created with the body force (same
+    reference densities, so the FP32 shifted storage is carried over
+    exactly).  Returns the time series of both phases."""
+    import sc_inputs
+    R = L / 4.0
+    fl = sc_inputs.drop(L, L, 1, radius=R, rho_in=(rho + 1.0) / 2.0, rho_out=(rho - 1.0) / 2.0,
+                        width=2.0, noise=0.0)
+    cx, cy, cz = fl.centre
+
+    def row(lat, k):
+        rA, rB, u, T = lat.moments(fields=True, allow_nonfinite=True)
+        phi = rA - rB
+        return {"step": k, "sigma": T["R_eff"] * T["dp"], "dp": T["dp"], "R_eff": T["R_eff"],
+                "max_u": T["max_u"], "ke": T["ke"], "n_phi_pos": T["n_phi_pos"],
+                "phi_in": float(phi[0, int(cy), int(cx)]), "phi_out": float(phi[0, 0, 0]),
+                "mass_A": T["mass_A"], "n_nonfinite": T["n_nonfinite"]}
+
+    lat = Lattice(9, L, L, 1, tau_A=tau, G=G, precision=precision)
+    lat.init(fl.rho_A, fl.rho_B)
+    lat.set_probe(cx, cy, cz, R)
+    static = [row(lat, 0)]
+    for k in range(every, steps_static + 1, every):
+        lat.step(every)
+        static.append(row(lat, k))
+    f = lat.get_populations()
+    ref = lat.rho_ref
+    lat.close()
+
+    lat = Lattice(9, L, L, 1, tau_A=tau, G=G, precision=precision, rho_ref=ref, body_A=A)
+    lat.set_populations(f)
+    lat.set_probe(cx, cy, cz, R)
+    forced = [row(lat, 0)]
+    for k in range(every, steps_forced + 1, every):
+        lat.step(every)
+        forced.append(row(lat, k))
+    lat.close()
+    m0 = forced[0]["n_phi_pos"]
+    for r in forced:
+        r["leakage"] = r["n_phi_pos"] / m0
+    nu = (tau - 0.5) / 3.0
+    k = 2.0 * np.pi / L
+    return {"static": static, "forced": forced,
+            # single-phase Kolmogorov flow at the same forcing: u = A / (nu k^2) sin(k y),
+            # sum_x |u|^2 = N (A / (nu k^2))^2 / 2
+            "ke_single_phase": L * L * (A / (nu * k * k)) ** 2 / 2.0}
+
+
 def compare_drop(res: Dict[str, dict]) -> dict:
     a, b = res["fp64"], res["fp32_shifted"]
     ta, tb = a["totals"], b["totals"]
@@ -103,7 +164,7 @@ if __name__ == "__main__":
     import argparse
     import json
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["spinodal", "drop"])
+    ap.add_argument("study", choices=["spinodal", "drop", "paper"])
     ap.add_argument("--L", type=int, default=None)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--every", type=int, default=500)
@@ -117,6 +178,14 @@ if __name__ == "__main__":
         l64, l32 = r["fp64"][-1]["domain_length"], r["fp32_shifted"][-1]["domain_length"]
         print(json.dumps({"final_rel_domain_length_diff": abs(l32 - l64) / l64,
                           "wall_s": time.time() - t0}))
-    else:
+    elif a.study == "drop":
         r = drop_study(L=a.L or 128, steps=a.steps or 1000)
         print(json.dumps(compare_drop(r)))
+    else:
+        for prec in ("fp64", "fp32_shifted"):
+            r = paper_drop_kolmogorov(prec, every=a.every)
+            for phase in ("static", "forced"):
+                for row in r[phase]:
+                    print(json.dumps({"precision": prec, "phase": phase, **row}), flush=True)
+            print(json.dumps({"precision": prec, "ke_single_phase": r["ke_single_phase"],
+                              "wall_s": time.time() - t0}), flush=True)
