@@ -64,11 +64,11 @@ def lib():
         L.oracle_init.argtypes = [i, i, i, i, dp, dp, dp, dp]
         L.oracle_moments.argtypes = [i, i, i, i, dp, dp, dp]
         L.oracle_force.argtypes = [i, i, i, i, d, dp, dp]
-        L.oracle_collide.argtypes = [i, i, i, i, d, d, d, d, dp, dp]
+        L.oracle_collide.argtypes = [i, i, i, i, d, d, d, d, dp, dp, i]
         L.oracle_stream.argtypes = [i, i, i, i, dp, dp]
-        L.oracle_run.argtypes = [i, i, i, i, d, d, d, d, dp, i]
+        L.oracle_run.argtypes = [i, i, i, i, d, d, d, d, dp, i, i]
         L.oracle_observables.argtypes = [i, i, i, i, d, d, d, d, dp, dp, dp, dp, dp, dp]
-        L.oracle_step_sites.argtypes = [i, i, i, i, d, d, d, d, dp, lp, i, dp]
+        L.oracle_step_sites.argtypes = [i, i, i, i, d, d, d, d, dp, lp, i, dp, i]
         for fn in ("oracle_lattice", "oracle_feq", "oracle_init", "oracle_moments",
                    "oracle_force", "oracle_collide", "oracle_stream", "oracle_run",
                    "oracle_observables", "oracle_step_sites"):
@@ -141,13 +141,25 @@ def force(q: int, G: float, rho: np.ndarray) -> np.ndarray:
     return F
 
 
-def collide(f: np.ndarray, tau_A: float, tau_B: float, G: float, body_A: float = 0.0):
+FORCING = {"shift": 0, "guo": 1}
+
+
+def _forcing(name: str) -> int:
+    if name not in FORCING:
+        raise ValueError(f"forcing must be one of {sorted(FORCING)}")
+    return FORCING[name]
+
+
+def collide(f: np.ndarray, tau_A: float, tau_B: float, G: float, body_A: float = 0.0,
+            forcing: str = "shift"):
+    """One collision of both species; forcing "shift" is the paper's velocity
+    shift (Sec. 2.1), "guo" the discrete forcing it cites (Sec. 2.3)."""
     q = f.shape[1]
     nx, ny, nz = _dims(f.shape[2:])
     f = np.ascontiguousarray(f)
     out = np.zeros_like(f)
-    _check(lib().oracle_collide(q, nx, ny, nz, tau_A, tau_B, G, body_A, _p(f), _p(out)),
-           "collide")
+    _check(lib().oracle_collide(q, nx, ny, nz, tau_A, tau_B, G, body_A, _p(f), _p(out),
+                                _forcing(forcing)), "collide")
     return out
 
 
@@ -161,12 +173,13 @@ def stream(fpost: np.ndarray) -> np.ndarray:
 
 
 def run(f: np.ndarray, tau_A: float, tau_B: float, G: float, steps: int,
-        body_A: float = 0.0) -> np.ndarray:
+        body_A: float = 0.0, forcing: str = "shift") -> np.ndarray:
     """``steps`` full collide+stream steps; returns a new array."""
     q = f.shape[1]
     nx, ny, nz = _dims(f.shape[2:])
     g = np.array(f, dtype=np.float64, order="C", copy=True)
-    _check(lib().oracle_run(q, nx, ny, nz, tau_A, tau_B, G, body_A, _p(g), steps), "run")
+    _check(lib().oracle_run(q, nx, ny, nz, tau_A, tau_B, G, body_A, _p(g), steps,
+                            _forcing(forcing)), "run")
     return g
 
 
@@ -188,7 +201,7 @@ def observables(f: np.ndarray, tau_A: float, tau_B: float, G: float, probe=None,
 
 
 def step_sites(f: np.ndarray, tau_A: float, tau_B: float, G: float, sites: np.ndarray,
-               body_A: float = 0.0) -> np.ndarray:
+               body_A: float = 0.0, forcing: str = "shift") -> np.ndarray:
     """Populations after one step at the given flat site indices: out[k, s, i]."""
     q = f.shape[1]
     nx, ny, nz = _dims(f.shape[2:])
@@ -197,5 +210,5 @@ def step_sites(f: np.ndarray, tau_A: float, tau_B: float, G: float, sites: np.nd
     _check(lib().oracle_step_sites(q, nx, ny, nz, tau_A, tau_B, G, body_A,
                                    _p(np.ascontiguousarray(f)),
                                    sites.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
-                                   len(sites), _p(out)), "step_sites")
+                                   len(sites), _p(out), _forcing(forcing)), "step_sites")
     return out

@@ -25,8 +25,10 @@
  * conservation laws, fixed points, shear-wave and interdiffusion decay rates,
  * the linearised Fourier-mode update, the continuum growth rate of the
  * paper's chemical potential, the worked example's bulk order parameter and
- * Laplace-law linearity), and cross-checked against an independent NumPy
- * implementation on small grids.
+ * Laplace-law linearity; for the Guo forcing option: exact mass and
+ * momentum balance, the laminar Kolmogorov profile, and the linearised growth
+ * rate with the bare coupling g in place of g^(tau)), and cross-checked
+ * against an independent NumPy implementation on small grids.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -209,13 +211,39 @@ static double kolmogorov(double A, int y, int ny) {
     return A * sin(2.0 * M_PI * (double)y / (double)ny);
 }
 
-/* One BGK collision of both species (eq:be, right-hand side):
+/* Forcing schemes.  ORACLE_FORCING_SHIFT is the paper's (Sec. 2.1): the
+ * force enters only through the shifted equilibrium velocity v_s.
+ * ORACLE_FORCING_GUO is the discrete forcing of Guo, Zheng and Shi (2002),
+ * which the paper cites as the way to remove the tau-dependence of the
+ * effective coupling g^(tau) = tau g / (tau - 1/2) (Sec. 2.3).  The paper
+ * gives no formula for it; this is the standard form applied per species:
+ *   u      = sum_s (j_s + F_s / 2) / tau_s  /  sum_s rho_s / tau_s
+ *   f*_is  = f_is - (f_is - f^eq_is(rho_s, u)) / tau_s + S_is
+ *   S_is   = (1 - 1 / (2 tau_s)) w_i [ (c_i - u).F_s / c_S^2
+ *                                      + (c_i.u)(c_i.F_s) / c_S^4 ]
+ * Sum_i S_is = 0 and sum_i S_is c_i = (1 - 1/(2 tau_s)) F_s, so the step
+ * conserves each species' mass and adds exactly sum_s F_s of momentum. */
+enum { ORACLE_FORCING_SHIFT = 0, ORACLE_FORCING_GUO = 1 };
+
+static double guo_source(const lat_t *L, int i, const double u[3], const double F[3],
+                         double tau) {
+    double cu = 0.0, cF = 0.0, uF = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        cu += L->c[i][a] * u[a];
+        cF += L->c[i][a] * F[a];
+        uF += u[a] * F[a];
+    }
+    return (1.0 - 1.0 / (2.0 * tau)) * L->w[i] * ((cF - uF) / CS2 + cu * cF / (CS2 * CS2));
+}
+
+/* One BGK collision of both species (eq:be, right-hand side).  Velocity
+ * shift (the paper's scheme):
  *   u    = sum_s (1/tau_s) j_s / sum_s (1/tau_s) rho_s       (common velocity)
  *   v_s  = u + tau_s F_s / rho_s                              (force shift)
- *   f*_is = f_is - (f_is - f_is^eq(rho_s, v_s)) / tau_s.
- * fpost may not alias f. */
+ *   f*_is = f_is - (f_is - f_is^eq(rho_s, v_s)) / tau_s;
+ * Guo forcing as described above.  fpost may not alias f. */
 int oracle_collide(int q, int nx, int ny, int nz, double tauA, double tauB, double G,
-                   double bodyA, const double *f, double *fpost) {
+                   double bodyA, const double *f, double *fpost, int forcing) {
     lat_t L;
     if (lat_make(&L, q, nx, ny, nz) != 0) return -1;
     double *rho = malloc(sizeof(double) * 2 * L.n);
@@ -235,6 +263,27 @@ int oracle_collide(int q, int nx, int ny, int nz, double tauA, double tauB, doub
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long site = ((long)z * ny + y) * nx + x;
+                if (forcing == ORACLE_FORCING_GUO) {
+                    double Fs[2][3], num[3] = {0.0, 0.0, 0.0}, den = 0.0;
+                    for (int s = 0; s < 2; ++s) {
+                        double r = rho[s * L.n + site];
+                        for (int a = 0; a < 3; ++a) Fs[s][a] = F[(s * 3 + a) * L.n + site];
+                        if (bodyA != 0.0) Fs[s][0] += r * kolmogorov(bodyA, y, ny);
+                        for (int a = 0; a < 3; ++a)
+                            num[a] += (j[(s * 3 + a) * L.n + site] + 0.5 * Fs[s][a]) / tau[s];
+                        den += r / tau[s];
+                    }
+                    double u[3] = {num[0] / den, num[1] / den, num[2] / den};
+                    for (int s = 0; s < 2; ++s) {
+                        feq_at(&L, rho[s * L.n + site], u, feq);
+                        for (int i = 0; i < q; ++i) {
+                            double fi = f[fidx(&L, s, i, site)];
+                            fpost[fidx(&L, s, i, site)] =
+                                fi - (fi - feq[i]) / tau[s] + guo_source(&L, i, u, Fs[s], tau[s]);
+                        }
+                    }
+                    continue;
+                }
                 double num[3] = {0.0, 0.0, 0.0}, den = 0.0;
                 for (int s = 0; s < 2; ++s) {
                     for (int a = 0; a < 3; ++a) num[a] += j[(s * 3 + a) * L.n + site] / tau[s];
@@ -280,13 +329,13 @@ int oracle_stream(int q, int nx, int ny, int nz, const double *fpost, double *fn
 
 /* nsteps full time steps (collide, then stream), in place on f. */
 int oracle_run(int q, int nx, int ny, int nz, double tauA, double tauB, double G,
-               double bodyA, double *f, int nsteps) {
+               double bodyA, double *f, int nsteps, int forcing) {
     lat_t L;
     if (lat_make(&L, q, nx, ny, nz) != 0 || nsteps < 0) return -1;
     double *tmp = malloc(sizeof(double) * 2 * q * L.n);
     if (!tmp) return -2;
     for (int t = 0; t < nsteps; ++t) {
-        oracle_collide(q, nx, ny, nz, tauA, tauB, G, bodyA, f, tmp);
+        oracle_collide(q, nx, ny, nz, tauA, tauB, G, bodyA, f, tmp, forcing);
         oracle_stream(q, nx, ny, nz, tmp, f);
     }
     free(tmp);
@@ -416,7 +465,7 @@ int oracle_observables(int q, int nx, int ny, int nz, double tauA, double tauB, 
  * lattices where a full oracle step is too slow to run in a test. */
 int oracle_step_sites(int q, int nx, int ny, int nz, double tauA, double tauB, double G,
                       double bodyA, const double *f, const long *sites, int nsites,
-                      double *out) {
+                      double *out, int forcing) {
     lat_t L;
     if (lat_make(&L, q, nx, ny, nz) != 0) return -1;
     const double tau[2] = {tauA, tauB};
@@ -452,6 +501,21 @@ int oracle_step_sites(int q, int nx, int ny, int nz, double tauA, double tauB, d
                 }
                 for (int a = 0; a < 3; ++a) Fs[s][a] = -G * rho[s] * sum[a];
                 if (bodyA != 0.0) Fs[s][0] += rho[s] * kolmogorov(bodyA, y0, ny);
+            }
+            if (forcing == ORACLE_FORCING_GUO) {
+                double num[3] = {0.0, 0.0, 0.0}, den = 0.0;
+                for (int s = 0; s < 2; ++s) {
+                    for (int a = 0; a < 3; ++a) num[a] += (j[s][a] + 0.5 * Fs[s][a]) / tau[s];
+                    den += rho[s] / tau[s];
+                }
+                double u[3] = {num[0] / den, num[1] / den, num[2] / den};
+                for (int s = 0; s < 2; ++s) {
+                    feq_at(&L, rho[s], u, feq);
+                    double fi = f[fidx(&L, s, i, up)];
+                    out[(long)k * 2 * q + s * q + i] =
+                        fi - (fi - feq[i]) / tau[s] + guo_source(&L, i, u, Fs[s], tau[s]);
+                }
+                continue;
             }
             double num[3] = {0.0, 0.0, 0.0}, den = 0.0;
             for (int s = 0; s < 2; ++s) {

@@ -54,7 +54,8 @@ def _shift(a: np.ndarray, c) -> np.ndarray:
     return np.roll(a, shift=(-int(c[2]), -int(c[1]), -int(c[0])), axis=(-3, -2, -1))
 
 
-def step(f: np.ndarray, tau_A: float, tau_B: float, G: float, body_A: float = 0.0):
+def step(f: np.ndarray, tau_A: float, tau_B: float, G: float, body_A: float = 0.0,
+         forcing: str = "shift"):
     q = f.shape[1]
     c, w = velocity_set(q)
     cf = c.astype(np.float64)
@@ -72,8 +73,23 @@ def step(f: np.ndarray, tau_A: float, tau_B: float, G: float, body_A: float = 0.
         y = np.arange(ny, dtype=np.float64).reshape(1, ny, 1)
         F[:, 0] += rho * body_A * np.sin(2.0 * np.pi * y / ny)
     tau = np.array([tau_A, tau_B])
-    u = (j / tau[:, None, None, None, None]).sum(0) / (rho / tau[:, None, None, None]).sum(0)
     out = np.empty_like(f)
+    if forcing == "guo":
+        # equilibrium at the common velocity of the half-force corrected momenta,
+        # plus each species' discrete forcing term (Hermite projection of F_s)
+        u = ((j + 0.5 * F) / tau[:, None, None, None, None]).sum(0) / \
+            (rho / tau[:, None, None, None]).sum(0)
+        cu = np.einsum("ia,azyx->izyx", cf, u)
+        for s in range(2):
+            cF = np.einsum("ia,azyx->izyx", cf, F[s])
+            uF = (u * F[s]).sum(0)
+            src = w.reshape(-1, 1, 1, 1) * ((cF - uF[None]) / CS2 + cu * cF / CS2**2)
+            fs = f[s] - (f[s] - equilibrium(q, rho[s], u)) / tau[s] + (1 - 0.5 / tau[s]) * src
+            for i in range(q):
+                out[s, i] = np.roll(fs[i], shift=(int(c[i, 2]), int(c[i, 1]), int(c[i, 0])),
+                                    axis=(-3, -2, -1))
+        return out
+    u = (j / tau[:, None, None, None, None]).sum(0) / (rho / tau[:, None, None, None]).sum(0)
     for s in range(2):
         v = u + tau[s] * F[s] / rho[s]
         fe = equilibrium(q, rho[s], v)
@@ -85,8 +101,8 @@ def step(f: np.ndarray, tau_A: float, tau_B: float, G: float, body_A: float = 0.
 
 
 def run(f: np.ndarray, tau_A: float, tau_B: float, G: float, steps: int,
-        body_A: float = 0.0) -> np.ndarray:
+        body_A: float = 0.0, forcing: str = "shift") -> np.ndarray:
     g = np.array(f, dtype=np.float64, copy=True)
     for _ in range(steps):
-        g = step(g, tau_A, tau_B, G, body_A)
+        g = step(g, tau_A, tau_B, G, body_A, forcing)
     return g

@@ -39,8 +39,13 @@ def vset(q):
 
 
 def update_matrix(q: int, k, rho_A0: float, rho_B0: float, tau_A: float, tau_B: float,
-                  G: float) -> np.ndarray:
-    """The 2Q x 2Q complex matrix M(k) acting on fhat[s*Q + i]."""
+                  G: float, forcing: str = "shift") -> np.ndarray:
+    """The 2Q x 2Q complex matrix M(k) acting on fhat[s*Q + i].
+
+    forcing "guo" linearises the discrete forcing instead of the velocity
+    shift: du = sum_s (dj_s + dF_s / 2) / tau_s / sum_s rho_s0 / tau_s, the
+    equilibrium at du for every species, plus the source
+    (1 - 1/(2 tau_s)) w_i c_i.dF_s / c_S^2 (its terms in u vanish at rest)."""
     c, w = vset(q)
     k = np.asarray(k, dtype=np.float64)
     phase = np.exp(1j * (c @ k))                       # e^{i k.c_i}
@@ -56,8 +61,16 @@ def update_matrix(q: int, k, rho_A0: float, rho_B0: float, tau_A: float, tau_B: 
         dj = fh @ c                                     # [s, 3]
         dgath = np.array([gvec * drho[1], gvec * drho[0]])
         dF = -G * rho0[:, None] * dgath
-        du = (dj / tau[:, None]).sum(0) / (rho0 / tau).sum()
         out = np.zeros((2, q), dtype=complex)
+        if forcing == "guo":
+            du = ((dj + 0.5 * dF) / tau[:, None]).sum(0) / (rho0 / tau).sum()
+            for s in range(2):
+                dfeq = w * (drho[s] + rho0[s] * (c @ du) / CS2)
+                dsrc = (1.0 - 0.5 / tau[s]) * w * (c @ dF[s]) / CS2
+                out[s] = np.conj(phase) * ((1.0 - 1.0 / tau[s]) * fh[s] + dfeq / tau[s] + dsrc)
+            M[:, col] = out.reshape(-1)
+            continue
+        du = (dj / tau[:, None]).sum(0) / (rho0 / tau).sum()
         for s in range(2):
             dv = du + tau[s] * dF[s] / rho0[s]
             dfeq = w * (drho[s] + rho0[s] * (c @ dv) / CS2)
@@ -67,14 +80,14 @@ def update_matrix(q: int, k, rho_A0: float, rho_B0: float, tau_A: float, tau_B: 
     return M
 
 
-def phi_mode_rate(q, k, rho, tau, G):
+def phi_mode_rate(q, k, rho, tau, G, forcing: str = "shift"):
     """Growth rate log(lambda) of the order-parameter mode at wavevector k.
 
     Base state rho_A0 = rho_B0 = rho/2; the phi mode is the eigenvector whose
     density perturbation is antisymmetric (drho_A = -drho_B) with the
     eigenvalue closest to 1.
     """
-    M = update_matrix(q, k, rho / 2, rho / 2, tau, tau, G)
+    M = update_matrix(q, k, rho / 2, rho / 2, tau, tau, G, forcing)
     lam, vec = np.linalg.eig(M)
     best = None
     for j in range(len(lam)):
@@ -89,15 +102,17 @@ def phi_mode_rate(q, k, rho, tau, G):
     return np.log(lam[best])
 
 
-def paper_phi_rate(k: float, rho: float, tau: float, G: float) -> float:
+def paper_phi_rate(k: float, rho: float, tau: float, G: float, coupling: str = "g_tau") -> float:
     """Continuum growth rate of a small phi mode from the paper's SC limit.
 
     Sec. 2.1: d phi/dt = div(M grad mu) with M = rho (tau - 1/2) at phi = 0 and
     mu^(tau) linearised about phi = 0:
       mu ~ (c_S^2 / rho) phi - (g^(tau)/2) c_S^2 phi - (g^(tau)/4) c_S^4 lap(phi),
-    g^(tau) = tau G / (tau - 1/2).  For phi ~ e^{ikx}:
+    g^(tau) = tau G / (tau - 1/2) (coupling "g_tau"; "g" puts the bare G in its
+    place, the limit the paper expects once the discrete forcing is cured).
+    For phi ~ e^{ikx}:
       omega = -M k^2 [c_S^2/rho - g^(tau) c_S^2/2 + g^(tau) c_S^4 k^2 / 4].
     """
-    gt = tau * G / (tau - 0.5)
+    gt = tau * G / (tau - 0.5) if coupling == "g_tau" else G
     M = rho * (tau - 0.5)
     return -M * k * k * (CS2 / rho - gt * CS2 / 2 + gt * CS2 * CS2 * k * k / 4)
