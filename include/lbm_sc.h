@@ -64,6 +64,22 @@ enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
  * moments, observables and reductions are still evaluated in FP64. */
 enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 };
 
+/* How the force F_s = psi_s a_s (+ the body force) enters the collision.
+ * LBM_FORCING_SHIFT: the paper's scheme (Sec. 2.1, eq:be): the equilibrium
+ *   of species s is taken at v_s = u' + tau_s F_s / rho_s, with the common
+ *   velocity u' = sum_s j_s / tau_s / sum_s rho_s / tau_s.  Its effective
+ *   coupling in the hydrodynamic limit is g^(tau) = tau g / (tau - 1/2).
+ * LBM_FORCING_GUO: the discrete forcing of Guo, Zheng and Shi, which the
+ *   paper cites as the way to remove that tau-dependence (Sec. 2.3; the paper
+ *   gives no formula, this is the standard per-species form):
+ *     u     = sum_s (j_s + F_s / 2) / tau_s / sum_s rho_s / tau_s
+ *     f*_is = f_is - (f_is - f^eq_is(rho_s, u)) / tau_s + S_is
+ *     S_is  = (1 - 1/(2 tau_s)) w_i [ (c_i - u).F_s / c_S^2
+ *                                     + (c_i.u)(c_i.F_s) / c_S^4 ]
+ *   Each species' mass is conserved and the momentum grows by exactly
+ *   sum_s F_s per step; the effective coupling is the bare g. */
+enum { LBM_FORCING_SHIFT = 0, LBM_FORCING_GUO = 1 };
+
 enum {
     LBM_OK = 0,
     LBM_EINVAL = -1,      /* bad argument */
@@ -83,7 +99,8 @@ enum {
  *   rho_ref_A, rho_ref_B: FP32_SHIFTED reference densities; a value <= 0
  *   means "the volume mean of the densities passed to lbm_sc_init";
  *   body_A: amplitude A of the Kolmogorov body force of Sec. 4.2,
- *   F_x += rho_s A sin(2 pi y / ny) on each species (0 disables it). */
+ *   F_x += rho_s A sin(2 pi y / ny) on each species (0 disables it);
+ *   forcing: LBM_FORCING_SHIFT (default) or LBM_FORCING_GUO. */
 typedef struct {
     int lattice;
     int nx, ny, nz;
@@ -92,6 +109,7 @@ typedef struct {
     int precision;
     double rho_ref_A, rho_ref_B;
     double body_A;
+    int forcing;
 } lbm_sc_params;
 
 /* FP64 totals of one state, all reduced on the GPU in a fixed order.
@@ -124,7 +142,8 @@ typedef struct {
     long long step;
 } lbm_sc_totals;
 
-/* Fills *p with FP64, no body force, automatic reference densities. */
+/* Fills *p with FP64, no body force, automatic reference densities, the
+ * velocity-shift forcing. */
 int lbm_sc_params_default(lbm_sc_params *p, int lattice, int nx, int ny, int nz,
                           double tau_A, double tau_B, double G);
 

@@ -15,6 +15,7 @@ LIB_PATH = os.environ.get("LBM_SC_LIB") or os.path.join(HERE, "liblbm_sc.so")
 
 LBM_D2Q9, LBM_D3Q19 = 9, 19
 LBM_FP64, LBM_FP32_SHIFTED = 0, 1
+LBM_FORCING_SHIFT, LBM_FORCING_GUO = 0, 1
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE = 0, -1, -2, -3
 LBM_ESTATE, LBM_ENONFINITE, LBM_EBUDGET, LBM_ETIMEOUT = -4, -5, -6, -7
 LBM_BATCH_PER_LATTICE, LBM_BATCH_FUSED, LBM_BATCH_PERSISTENT = 0, 1, 2
@@ -29,6 +30,7 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("rho_ref_A", ctypes.c_double), ("rho_ref_B", ctypes.c_double),
         ("body_A", ctypes.c_double),
+        ("forcing", ctypes.c_int),
     ]
 
 

@@ -1,10 +1,12 @@
 """Autotuner of the fused step's launch shape.
 
-For a lattice type, size and precision it times every compiled transverse
-tile with a set of march-chunk lengths on a scratch lattice (HIP events on
-the lattice's stream), keeps the fastest, and caches the choice in a JSON
-table keyed by "q:nx:ny:nz:precision".  Lattices look their configuration up
-by exact key, then by the nearest tuned size of the same type and precision.
+For a lattice type, size, precision and forcing scheme it times every
+compiled transverse tile with a set of march-chunk lengths on a scratch
+lattice (HIP events on the lattice's stream), keeps the fastest, and caches
+the choice in a JSON table keyed by "q:nx:ny:nz:precision" ("precision+guo"
+for the Guo forcing, whose kernels are separate instantiations).  Lattices
+look their configuration up by exact key, then by the nearest tuned size of
+the same type, precision and forcing, then (Guo) of the same precision.
 
 The tuned schedule feeds both single-lattice launches (Lattice.set_kernel)
 and batches (Batch.set_tiles with a tile whose block size D2Q9 and D3Q19
@@ -24,8 +26,12 @@ from .lattice import Lattice, tiles
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 
-def _key(q, nx, ny, nz, precision):
-    return f"{q}:{nx}:{ny}:{nz}:{precision}"
+def _pkey(precision: str, forcing: str = "shift") -> str:
+    return precision if forcing == "shift" else f"{precision}+{forcing}"
+
+
+def _key(q, nx, ny, nz, precision, forcing: str = "shift"):
+    return f"{q}:{nx}:{ny}:{nz}:{_pkey(precision, forcing)}"
 
 
 def load(path: str = CACHE) -> Dict[str, dict]:
@@ -43,17 +49,22 @@ def save(table: Dict[str, dict], path: str = CACHE):
 
 
 def lookup(q: int, nx: int, ny: int, nz: int, precision: str,
-           table: Optional[Dict[str, dict]] = None) -> Optional[Tuple[int, int, int, int]]:
+           table: Optional[Dict[str, dict]] = None,
+           forcing: str = "shift") -> Optional[Tuple[int, int, int, int]]:
     """(variant, tx, ty, mb) for the lattice, or None if nothing of its type is tuned."""
     table = load() if table is None else table
-    k = _key(q, nx, ny, nz, precision)
+    k = _key(q, nx, ny, nz, precision, forcing)
     if k in table:
         e = table[k]
         return (e["variant"], e["tx"], e["ty"], e["mb"])
+    pk = _pkey(precision, forcing)
+    if forcing != "shift" and not any(key.split(":")[0] == str(q) and key.split(":")[4] == pk
+                                      for key in table):
+        pk = precision                 # nothing tuned for this scheme: the shift's choice
     best, bd = None, math.inf
     for key, e in table.items():
         kq, kx, ky, kz, kp = key.split(":")
-        if int(kq) != q or kp != precision:
+        if int(kq) != q or kp != pk:
             continue
         d = abs(math.log(int(kx) * int(ky) * int(kz) / (nx * ny * nz)))
         if d < bd:
@@ -71,14 +82,14 @@ def _mb_candidates(march: int) -> List[int]:
 
 def tune(q: int, nx: int, ny: int, nz: int = 1, *, precision: str = "fp64", G: float = 1.6,
          tau: float = 1.0, steps: int = 20, warmup: int = 3, mbs: Optional[Iterable[int]] = None,
-         include_twopass: bool = True, verbose: bool = False) -> dict:
+         include_twopass: bool = True, verbose: bool = False, forcing: str = "shift") -> dict:
     """Times the candidates on a scratch spinodal lattice; returns the best entry
     plus the full table of timings (ms per step)."""
     rng = np.random.default_rng(0)
     shape = (nz, ny, nx)
     rA = 0.5 + rng.uniform(-0.01, 0.01, shape)
     rB = 0.5 + rng.uniform(-0.01, 0.01, shape)
-    lat = Lattice(q, nx, ny, nz, tau_A=tau, G=G, precision=precision)
+    lat = Lattice(q, nx, ny, nz, tau_A=tau, G=G, precision=precision, forcing=forcing)
     lat.init(rA, rB)
     march = nz if q == 19 else ny
     mbs = list(mbs) if mbs is not None else _mb_candidates(march)
@@ -114,7 +125,7 @@ def tune_and_store(specs, path: str = CACHE, **kw) -> Dict[str, dict]:
 def apply(lat: Lattice, table: Optional[Dict[str, dict]] = None) -> bool:
     """Sets the tuned configuration on a lattice; False if none is known."""
     nz, ny, nx = lat.shape
-    cfg = lookup(lat.q, nx, ny, nz, lat.precision, table)
+    cfg = lookup(lat.q, nx, ny, nz, lat.precision, table, getattr(lat, "forcing", "shift"))
     if cfg is None:
         return False
     lat.set_kernel(*cfg)
@@ -124,7 +135,8 @@ def apply(lat: Lattice, table: Optional[Dict[str, dict]] = None) -> bool:
 if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser(description="tune the fused step's tile and march chunk")
-    ap.add_argument("specs", nargs="+", help="q:nx:ny:nz:precision, e.g. 19:256:256:256:fp64")
+    ap.add_argument("specs", nargs="+",
+                    help="q:nx:ny:nz:precision[+guo], e.g. 19:256:256:256:fp64")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--store", action="store_true")
     ap.add_argument("--table", default=CACHE, help="JSON table to update (default: packaged)")
@@ -135,10 +147,12 @@ if __name__ == "__main__":
         specs.append((int(q), int(x), int(y), int(z), p))
     table = load(a.table)
     for spec in specs:
-        e = tune(*spec[:4], precision=spec[4], steps=a.steps, verbose=True)
+        prec, _, forcing = spec[4].partition("+")
+        forcing = forcing or "shift"
+        e = tune(*spec[:4], precision=prec, forcing=forcing, steps=a.steps, verbose=True)
         best = {k: v for k, v in e.items() if k != "candidates"}
         print(json.dumps(best), flush=True)
-        table[_key(*spec)] = best
+        table[_key(*spec[:4], prec, forcing)] = best
     if a.store:
         save(table, a.table)
 

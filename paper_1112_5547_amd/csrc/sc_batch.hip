@@ -186,7 +186,7 @@ struct Member {
     long long remaining;
 };
 
-// One precision group's device tables and cached graph.
+// One policy group's (precision, forcing) device tables and cached graph.
 struct Group {
     BatchDesc* d_desc = nullptr;
     size_t desc_cap = 0;
@@ -211,7 +211,7 @@ struct lbm_batch {
     std::vector<Member> members;
     int nt = 256, tx19 = 64, ty19 = 4;
     int mb9 = 0, mb19 = 0;  // 0: each member's own march chunk
-    Group grp[2];           // FP64, FP32-shifted
+    Group grp[4];           // by step_policy: FP64, FP32-shifted, and their Guo forms
     int err = 0;
 };
 
@@ -286,7 +286,7 @@ int member_mb(const lbm_batch* b, const lbm_sc* h) {
     return o > 0 ? o : h->mb;
 }
 
-// Enqueues one epoch of the members of one precision group.
+// Enqueues one epoch of the members of one policy group (precision and forcing).
 int run_group(lbm_batch* b, int prec, const std::vector<int>& idx, const std::vector<int>& ksteps,
               int K, int mode) {
     Group& g = b->grp[prec];
@@ -338,8 +338,10 @@ int run_group(lbm_batch* b, int prec, const std::vector<int>& idx, const std::ve
 
     StepFn sf = nullptr;
     PersFn pf = nullptr;
-    const bool ok = prec == 0 ? lookup_fns<PF64>(b->nt, b->tx19, b->ty19, &sf, &pf)
-                              : lookup_fns<PF32S>(b->nt, b->tx19, b->ty19, &sf, &pf);
+    const bool ok = prec == 0   ? lookup_fns<PF64>(b->nt, b->tx19, b->ty19, &sf, &pf)
+                    : prec == 1 ? lookup_fns<PF32S>(b->nt, b->tx19, b->ty19, &sf, &pf)
+                    : prec == 2 ? lookup_fns<PF64G>(b->nt, b->tx19, b->ty19, &sf, &pf)
+                                : lookup_fns<PF32SG>(b->nt, b->tx19, b->ty19, &sf, &pf);
     if (!ok) return LBM_EINVAL;
 
     int grid = nwork;
@@ -461,17 +463,17 @@ int lbm_batch_run(lbm_batch* b, int epoch_steps, int mode) {
         return LBM_EINVAL;
     if (epoch_steps == 0) return LBM_OK;
     (void)hipSetDevice(b->device);
-    std::vector<int> idx[2], ks[2];
+    std::vector<int> idx[4], ks[4];
     for (size_t i = 0; i < b->members.size(); ++i) {
         Member& m = b->members[i];
         if (m.remaining <= 0 || m.h->err) continue;
         const int k = (int)std::min<long long>(m.remaining, epoch_steps);
-        const int prec = m.h->p.precision == LBM_FP64 ? 0 : 1;
+        const int prec = step_policy(m.h->p.precision, m.h->p.forcing);
         idx[prec].push_back((int)i);
         ks[prec].push_back(k);
     }
     if (mode == LBM_BATCH_PER_LATTICE) {
-        for (int prec = 0; prec < 2; ++prec)
+        for (int prec = 0; prec < 4; ++prec)
             for (size_t m = 0; m < idx[prec].size(); ++m) {
                 lbm_sc* h = b->members[idx[prec][m]].h;
                 lbm_batch* keep = h->batch;
@@ -486,7 +488,7 @@ int lbm_batch_run(lbm_batch* b, int epoch_steps, int mode) {
             }
         return LBM_OK;
     }
-    for (int prec = 0; prec < 2; ++prec) {
+    for (int prec = 0; prec < 4; ++prec) {
         if (idx[prec].empty()) continue;
         const int K = *std::max_element(ks[prec].begin(), ks[prec].end());
         const int rc = run_group(b, prec, idx[prec], ks[prec], K, mode);
@@ -507,7 +509,7 @@ int lbm_batch_poll(lbm_batch* b, lbm_sc** done, int max_done, int* n_done) {
     if (b->err) return b->err;
     (void)hipSetDevice(b->device);
     BCALL(b, hipStreamSynchronize(b->stream));
-    for (int prec = 0; prec < 2; ++prec) {
+    for (int prec = 0; prec < 4; ++prec) {
         Group& g = b->grp[prec];
         if (g.d_sync && g.g_mode == LBM_BATCH_PERSISTENT) {
             unsigned flag = 0;

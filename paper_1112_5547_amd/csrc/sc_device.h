@@ -98,13 +98,23 @@ struct PF64 {
     using T = double;
     using A = double;
     static constexpr bool shifted = false;
+    static constexpr bool guo = false;   // force through the velocity shift
     static constexpr int code = 0;
 };
 struct PF32S {
     using T = float;
     using A = float;
     static constexpr bool shifted = true;
+    static constexpr bool guo = false;
     static constexpr int code = 1;
+};
+// The same storage with the Guo discrete forcing: the step kernels are
+// instantiated per forcing scheme, so neither pays for the other's registers.
+struct PF64G : PF64 {
+    static constexpr bool guo = true;
+};
+struct PF32SG : PF32S {
+    static constexpr bool guo = true;
 };
 
 // Everything a step of one lattice needs; passed by value into kernels or
@@ -122,6 +132,7 @@ struct StepParams {
     double G;
     double rho_ref[2];
     double body_A;
+    int forcing;        // 0: velocity shift (Sec. 2.1), 1: Guo (selects the kernel policy)
 };
 
 // Broadcast of block-uniform values into scalar registers.  Batched launches
@@ -228,6 +239,7 @@ __device__ __forceinline__ StepParams uniform_params(const StepParams& q) {
     }
     p.G = unid(q.G);
     p.body_A = unid(q.body_A);
+    p.forcing = (int)uni32((uint32_t)q.forcing);
     return p;
 }
 
@@ -270,16 +282,73 @@ __device__ __forceinline__ void gather(Rho&& rho, A (&g)[2][3]) {
 //   f      : the site's pulled populations f_is(x, t) (shifted h_is in FP32 mode)
 //   g[s]   : sum_i w_i rho_s(x + c_i) c_i, the gather of species s
 //   body   : external acceleration along x (0 without forcing)
+// The force on species s is F_s = rho_s a_s with a_s = -G g[s'] + body x.
+// Velocity shift (p.forcing == 0, the paper's scheme): the equilibrium of s
+// is taken at v_s = u' + tau_s a_s, u' = sum_s j_s/tau_s / sum_s rho_s/tau_s.
+// Guo forcing (p.forcing == 1): both species' equilibria at the common
+// u = sum_s (j_s + F_s/2)/tau_s / sum_s rho_s/tau_s, plus the source
+// S_is = (1 - 1/(2 tau_s)) w_i [3 (c_i - u).F_s + 9 (c_i.u)(c_i.F_s)].
 // Stores f*_is at byte offset soff + voff of the (s, i) arrays of dst.  Every
 // launch form (fused, two-pass, batched, persistent) calls this function, so
 // the per-site arithmetic is identical across them.
+// Relaxation and store of species S at equilibrium velocity v; with GUO the
+// discrete forcing source of force F (u = v) is added.
+template <int Q, class PR, bool GUO>
+__device__ __forceinline__ void relax_store(const typename PR::T (&fs)[Q], int s,
+                                            const typename PR::A (&v)[3],
+                                            const typename PR::A (&F)[3], typename PR::A rho,
+                                            typename PR::A rfull, typename PR::A om,
+                                            char* __restrict__ dst, uint32_t pbytes,
+                                            uint32_t voff, uint32_t soff) {
+    using T = typename PR::T;
+    using A = typename PR::A;
+    const A vv = fmaa(v[0], v[0], fmaa(v[1], v[1], v[2] * v[2]));
+    const A base = fmaa(A(-1.5), vv, A(1));
+    // Guo source with the factor (1 - 1/(2 tau)) folded into the force:
+    // S_i = w_i [cF (9 cu + 3) - 3 u.F], F scaled
+    A Fp[3] = {A(0), A(0), A(0)}, uF3 = A(0);
+    if (GUO) {
+        const A pre = fmaa(A(-0.5), om, A(1));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Fp[a] = pre * F[a];
+        uF3 = A(3) * fmaa(v[0], Fp[0], fmaa(v[1], Fp[1], v[2] * Fp[2]));
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        A cu = A(0);
+        if (VSet<Q>::cx(i)) cu += VSet<Q>::cx(i) > 0 ? v[0] : -v[0];
+        if (VSet<Q>::cy(i)) cu += VSet<Q>::cy(i) > 0 ? v[1] : -v[1];
+        if (VSet<Q>::cz(i)) cu += VSet<Q>::cz(i) > 0 ? v[2] : -v[2];
+        const A wi = A(VSet<Q>::w(i));
+        A feq;
+        if (PR::shifted) {
+            // h^eq = f^eq - w rho_ref = w [delta + rho (3cu + 4.5cu^2 - 1.5vv)]
+            const A poly = fmaa(A(4.5) * cu, cu, fmaa(A(3), cu, A(-1.5) * vv));
+            feq = wi * fmaa(rfull, poly, rho);
+        } else {
+            feq = wi * rfull * fmaa(A(4.5) * cu, cu, fmaa(A(3), cu, base));
+        }
+        const A fv = A(fs[i]);
+        A fo = fmaa(om, feq - fv, fv);
+        if (GUO) {
+            A cF = A(0);
+            if (VSet<Q>::cx(i)) cF += VSet<Q>::cx(i) > 0 ? Fp[0] : -Fp[0];
+            if (VSet<Q>::cy(i)) cF += VSet<Q>::cy(i) > 0 ? Fp[1] : -Fp[1];
+            if (VSet<Q>::cz(i)) cF += VSet<Q>::cz(i) > 0 ? Fp[2] : -Fp[2];
+            // (c_i - u).F / c_S^2 + (c_i.u)(c_i.F) / c_S^4 with c_S^2 = 1/3
+            const A t = fmaa(cF, fmaa(A(9), cu, A(3)), -uF3);
+            fo = fmaa(wi, t, fo);
+        }
+        buf_store_nt<T>(T(fo), make_rsrc(dst + (size_t)(s * Q + i) * pbytes, pbytes), voff, soff);
+    }
+}
+
 template <int Q, class PR>
 __device__ __forceinline__ void collide_store(const typename PR::T (&f)[2][Q],
                                               const typename PR::A (&g)[2][3],
                                               const StepParams& p, double body,
                                               char* __restrict__ dst, uint32_t pbytes,
                                               uint32_t voff, uint32_t soff) {
-    using T = typename PR::T;
     using A = typename PR::A;
     pbytes = opaque_sgpr(pbytes);
     const A om[2] = {A(p.omega[0]), A(p.omega[1])};
@@ -303,40 +372,45 @@ __device__ __forceinline__ void collide_store(const typename PR::T (&f)[2][Q],
         j[s][1] = jy;
         j[s][2] = jz;
     }
-    // common velocity weighted by 1/tau_s, then the force shift of each species
-    const A den = fmaa(rfull[0], om[0], rfull[1] * om[1]);
-    A u[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = fmaa(j[0][a], om[0], j[1][a] * om[1]) / den;
+    // accelerations a_s = -G g[s'] + body (F_s = rho_s a_s)
     const A bx = A(body);
+    A acc[2][3];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const int so = 1 - s;
-        A v[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) v[a] = fmaa(tau[s], -G * g[so][a], u[a]);
-        v[0] = fmaa(tau[s], bx, v[0]);
-        const A vv = fmaa(v[0], v[0], fmaa(v[1], v[1], v[2] * v[2]));
-        const A base = fmaa(A(-1.5), vv, A(1));
+        for (int a = 0; a < 3; ++a) acc[s][a] = -G * g[1 - s][a];
+        acc[s][0] += bx;
+    }
+    const A den = fmaa(rfull[0], om[0], rfull[1] * om[1]);
+    if constexpr (PR::guo) {
+        // Guo: common velocity of the momenta corrected by half the force
+        A u[3];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            A cu = A(0);
-            if (VSet<Q>::cx(i)) cu += VSet<Q>::cx(i) > 0 ? v[0] : -v[0];
-            if (VSet<Q>::cy(i)) cu += VSet<Q>::cy(i) > 0 ? v[1] : -v[1];
-            if (VSet<Q>::cz(i)) cu += VSet<Q>::cz(i) > 0 ? v[2] : -v[2];
-            const A wi = A(VSet<Q>::w(i));
-            A feq;
-            if (PR::shifted) {
-                // h^eq = f^eq - w rho_ref = w [delta + rho (3cu + 4.5cu^2 - 1.5vv)]
-                const A poly = fmaa(A(4.5) * cu, cu, fmaa(A(3), cu, A(-1.5) * vv));
-                feq = wi * fmaa(rfull[s], poly, rho[s]);
-            } else {
-                feq = wi * rfull[s] * fmaa(A(4.5) * cu, cu, fmaa(A(3), cu, base));
-            }
-            const A fv = A(f[s][i]);
-            const A fo = fmaa(om[s], feq - fv, fv);
-            buf_store_nt<T>(T(fo), make_rsrc(dst + (size_t)(s * Q + i) * pbytes, pbytes), voff,
-                            soff);
+        for (int a = 0; a < 3; ++a) {
+            const A mA = fmaa(A(0.5) * rfull[0], acc[0][a], j[0][a]);
+            const A mB = fmaa(A(0.5) * rfull[1], acc[1][a], j[1][a]);
+            u[a] = fmaa(mA, om[0], mB * om[1]) / den;
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            A F[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) F[a] = rfull[s] * acc[s][a];
+            relax_store<Q, PR, true>(f[s], s, u, F, rho[s], rfull[s], om[s], dst, pbytes, voff,
+                                     soff);
+        }
+    } else {
+        // velocity shift: common velocity u', then v_s = u' + tau_s a_s
+        A u[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[a] = fmaa(j[0][a], om[0], j[1][a] * om[1]) / den;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            A v[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) v[a] = fmaa(tau[s], acc[s][a], u[a]);
+            relax_store<Q, PR, false>(f[s], s, v, v, rho[s], rfull[s], om[s], dst, pbytes, voff,
+                                      soff);
         }
     }
 }

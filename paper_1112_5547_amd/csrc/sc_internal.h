@@ -36,11 +36,15 @@ int tile_count(int Q);
 bool tile_get(int Q, int k, int* tx, int* ty);
 bool tile_supported(int Q, int tx, int ty);
 
-// single-lattice launches
-hipError_t launch_fused(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s);
-hipError_t launch_repull(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s);
-hipError_t launch_pipe(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s);
-hipError_t launch_twopass(int Q, int prec, const StepParams& p, void* psi, hipStream_t s);
+// Step-kernel policy index: storage precision (0 FP64, 1 FP32 shifted) plus
+// 2 for the Guo forcing (PF64, PF32S, PF64G, PF32SG).
+inline int step_policy(int precision, int forcing) { return precision + 2 * (forcing != 0); }
+
+// single-lattice launches (pol: step_policy)
+hipError_t launch_fused(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s);
+hipError_t launch_repull(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s);
+hipError_t launch_pipe(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s);
+hipError_t launch_twopass(int Q, int pol, const StepParams& p, void* psi, hipStream_t s);
 hipError_t launch_init(int Q, int prec, void* f, const double* rho, const double* u, int nx,
                        int ny, int nz, const double* rho_ref, hipStream_t s);
 hipError_t launch_get_plane(int Q, int prec, const void* f, double* out, int s_, int i, int nx,

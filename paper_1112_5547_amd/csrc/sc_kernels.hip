@@ -93,9 +93,14 @@ static hipError_t launch_fused_p(int Q, int tx, int ty, const StepParams& p, hip
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_fused(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s) {
-    return prec == 0 ? launch_fused_p<PF64>(Q, tx, ty, p, s)
-                     : launch_fused_p<PF32S>(Q, tx, ty, p, s);
+hipError_t launch_fused(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s) {
+    switch (pol) {
+        case 0: return launch_fused_p<PF64>(Q, tx, ty, p, s);
+        case 1: return launch_fused_p<PF32S>(Q, tx, ty, p, s);
+        case 2: return launch_fused_p<PF64G>(Q, tx, ty, p, s);
+        case 3: return launch_fused_p<PF32SG>(Q, tx, ty, p, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 // Pipelined march: three register planes; one wave per SIMD for D3Q19 FP64,
@@ -147,15 +152,22 @@ static hipError_t launch_pipe_p(int Q, int tx, int ty, const StepParams& p, hipS
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_pipe(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s) {
-    return prec == 0 ? launch_pipe_p<PF64>(Q, tx, ty, p, s) : launch_pipe_p<PF32S>(Q, tx, ty, p, s);
+hipError_t launch_pipe(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s) {
+    switch (pol) {
+        case 0: return launch_pipe_p<PF64>(Q, tx, ty, p, s);
+        case 1: return launch_pipe_p<PF32S>(Q, tx, ty, p, s);
+        case 2: return launch_pipe_p<PF64G>(Q, tx, ty, p, s);
+        case 3: return launch_pipe_p<PF32SG>(Q, tx, ty, p, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 
 // Re-pull march: one register plane; three waves per SIMD for FP64, four for FP32.
 template <int Q, class PR>
 struct RepullWaves {
-    static constexpr int value = PR::shifted ? 4 : 3;
+    // the Guo collision holds the force and its dot products: one wave less
+    static constexpr int value = (PR::shifted ? 4 : 3) - (PR::guo ? 1 : 0);
 };
 
 template <int Q, class PR, int TX, int TY>
@@ -200,9 +212,14 @@ static hipError_t launch_repull_p(int Q, int tx, int ty, const StepParams& p, hi
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_repull(int Q, int prec, int tx, int ty, const StepParams& p, hipStream_t s) {
-    return prec == 0 ? launch_repull_p<PF64>(Q, tx, ty, p, s)
-                     : launch_repull_p<PF32S>(Q, tx, ty, p, s);
+hipError_t launch_repull(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s) {
+    switch (pol) {
+        case 0: return launch_repull_p<PF64>(Q, tx, ty, p, s);
+        case 1: return launch_repull_p<PF32S>(Q, tx, ty, p, s);
+        case 2: return launch_repull_p<PF64G>(Q, tx, ty, p, s);
+        case 3: return launch_repull_p<PF32SG>(Q, tx, ty, p, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -301,10 +318,19 @@ static hipError_t launch_twopass_t(const StepParams& p, void* psi, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_twopass(int Q, int prec, const StepParams& p, void* psi, hipStream_t s) {
-    if (Q == 9)
-        return prec == 0 ? launch_twopass_t<9, PF64>(p, psi, s) : launch_twopass_t<9, PF32S>(p, psi, s);
-    return prec == 0 ? launch_twopass_t<19, PF64>(p, psi, s) : launch_twopass_t<19, PF32S>(p, psi, s);
+template <int Q>
+static hipError_t launch_twopass_q(int pol, const StepParams& p, void* psi, hipStream_t s) {
+    switch (pol) {
+        case 0: return launch_twopass_t<Q, PF64>(p, psi, s);
+        case 1: return launch_twopass_t<Q, PF32S>(p, psi, s);
+        case 2: return launch_twopass_t<Q, PF64G>(p, psi, s);
+        case 3: return launch_twopass_t<Q, PF32SG>(p, psi, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_twopass(int Q, int pol, const StepParams& p, void* psi, hipStream_t s) {
+    return Q == 9 ? launch_twopass_q<9>(pol, p, psi, s) : launch_twopass_q<19>(pol, p, psi, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -40,6 +40,7 @@ int validate(const lbm_sc_params* p) {
     if (!(p->G >= 0.0) || !isfinite(p->G)) return LBM_EINVAL;
     if (p->precision != LBM_FP64 && p->precision != LBM_FP32_SHIFTED) return LBM_EINVAL;
     if (!isfinite(p->body_A) || !isfinite(p->rho_ref_A) || !isfinite(p->rho_ref_B)) return LBM_EINVAL;
+    if (p->forcing != LBM_FORCING_SHIFT && p->forcing != LBM_FORCING_GUO) return LBM_EINVAL;
     return LBM_OK;
 }
 
@@ -129,15 +130,17 @@ StepParams sc_step_params(const lbm_sc* h, int parity) {
     sp.rho_ref[0] = h->rho_ref[0];
     sp.rho_ref[1] = h->rho_ref[1];
     sp.body_A = p.body_A;
+    sp.forcing = p.forcing;
     return sp;
 }
 
 hipError_t sc_launch_step(lbm_sc* h, int parity, hipStream_t s) {
     const StepParams sp = sc_step_params(h, parity);
-    if (h->variant == 1) return launch_twopass(h->Q, h->p.precision, sp, h->psi, s);
-    if (h->variant == 2) return launch_pipe(h->Q, h->p.precision, h->tx, h->ty, sp, s);
-    if (h->variant == 3) return launch_repull(h->Q, h->p.precision, h->tx, h->ty, sp, s);
-    return launch_fused(h->Q, h->p.precision, h->tx, h->ty, sp, s);
+    const int pol = step_policy(h->p.precision, h->p.forcing);
+    if (h->variant == 1) return launch_twopass(h->Q, pol, sp, h->psi, s);
+    if (h->variant == 2) return launch_pipe(h->Q, pol, h->tx, h->ty, sp, s);
+    if (h->variant == 3) return launch_repull(h->Q, pol, h->tx, h->ty, sp, s);
+    return launch_fused(h->Q, pol, h->tx, h->ty, sp, s);
 }
 
 namespace {
@@ -242,6 +245,7 @@ int lbm_sc_params_default(lbm_sc_params* p, int lattice, int nx, int ny, int nz,
     p->rho_ref_A = 0.0;
     p->rho_ref_B = 0.0;
     p->body_A = 0.0;
+    p->forcing = LBM_FORCING_SHIFT;
     return validate(p);
 }
 

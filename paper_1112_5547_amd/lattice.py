@@ -16,6 +16,7 @@ from ._abi import Params, Totals, check, dptr, lib
 
 _PREC = {"fp64": _abi.LBM_FP64, "fp32_shifted": _abi.LBM_FP32_SHIFTED,
          "f64": _abi.LBM_FP64, "f32s": _abi.LBM_FP32_SHIFTED}
+_FORCING = {"shift": _abi.LBM_FORCING_SHIFT, "guo": _abi.LBM_FORCING_GUO}
 
 
 class Lattice:
@@ -24,13 +25,14 @@ class Lattice:
     lattice: 9 (D2Q9, nz = 1) or 19 (D3Q19); tau_B defaults to tau_A;
     precision: "fp64" or "fp32_shifted"; rho_ref: (A, B) reference densities of
     the shifted storage (default: the mean of the initial densities);
-    body_A: Kolmogorov forcing amplitude (F_x = rho_s A sin(2 pi y / ny)).
+    body_A: Kolmogorov forcing amplitude (F_x = rho_s A sin(2 pi y / ny));
+    forcing: "shift" (the paper's velocity shift) or "guo" (Guo discrete forcing).
     """
 
     def __init__(self, lattice: int, nx: int, ny: int, nz: int = 1, *, tau_A: float = 1.0,
                  tau_B: Optional[float] = None, G: float = 0.0, precision: str = "fp64",
                  rho_ref: Optional[Tuple[float, float]] = None, body_A: float = 0.0,
-                 device: Optional[int] = None, use_torch: bool = True):
+                 forcing: str = "shift", device: Optional[int] = None, use_torch: bool = True):
         L = lib()
         p = Params()
         check(L.lbm_sc_params_default(ctypes.byref(p), lattice, nx, ny, nz, tau_A,
@@ -39,6 +41,10 @@ class Lattice:
         if rho_ref is not None:
             p.rho_ref_A, p.rho_ref_B = float(rho_ref[0]), float(rho_ref[1])
         p.body_A = float(body_A)
+        if forcing not in _FORCING:
+            raise ValueError(f"forcing must be one of {sorted(_FORCING)}")
+        p.forcing = _FORCING[forcing]
+        self.forcing = forcing
         self.params = p
         self.q = lattice
         self.shape = (nz, ny, nx)

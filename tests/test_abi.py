@@ -58,6 +58,16 @@ def test_params_validation_and_sizes():
     p.precision = _abi.LBM_FP32_SHIFTED
     need32 = L.lbm_sc_bytes_needed(ctypes.byref(p))
     assert need32 < need
+    # the forcing field sits where the C struct has it: the default fill
+    # overwrites it, and an unknown scheme is rejected
+    f = _abi.Params()
+    f.forcing = 7
+    assert L.lbm_sc_params_default(ctypes.byref(f), 9, 8, 8, 1, 1.0, 1.0, 1.0) == 0
+    assert f.forcing == _abi.LBM_FORCING_SHIFT and f.body_A == 0.0
+    f.forcing = _abi.LBM_FORCING_GUO
+    assert L.lbm_sc_bytes_needed(ctypes.byref(f)) > 0
+    f.forcing = 2
+    assert L.lbm_sc_bytes_needed(ctypes.byref(f)) == 0
     bad = [
         (9, 8, 8, 2, 1.0, 1.0, 1.0),     # D2Q9 with nz > 1
         (19, 0, 8, 8, 1.0, 1.0, 1.0),    # empty lattice

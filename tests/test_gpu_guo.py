@@ -1,0 +1,106 @@
+"""Guo discrete forcing on the GPU path (the forcing the paper cites as the
+cure for the tau-dependent coupling, Sec. 2.3): FP64 parity with the oracle
+(<= 1e-12 after the steps below), FP32 shifted within the FP32 bounds of the
+velocity-shift scheme, every kernel variant bitwise equal, a batch mixing both
+schemes bitwise equal to solo runs, and the scheme's defining property on a
+larger lattice: parameters that phase-separate under the velocity shift
+(rho g^(tau) > 2) are stable under Guo forcing (rho g < 2)."""
+import numpy as np
+import pytest
+
+import sc_inputs
+from gpu_common import gpu_run, maxabs, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("q,shape,steps", [(9, (1, 64, 64), 100), (19, (16, 20, 24), 60),
+                                           (9, (1, 37, 70), 80)])
+def test_guo_fp64_matches_oracle(q, shape, steps):
+    nz, ny, nx = shape
+    fl = sc_inputs.drop(nx, ny, nz, radius=min(nx, ny) / 4, seed=5)
+    say(f"guo fp64 q={q} {shape} {steps} steps")
+    lat, f = gpu_run(q, fl.rho_A, fl.rho_B, 0.7, 1.1, 1.3, steps, body_A=1e-5, forcing="guo")
+    lat.close()
+    ref = oracle_run(q, fl.rho_A, fl.rho_B, 0.7, 1.1, 1.3, steps, body_A=1e-5, forcing="guo")
+    assert maxabs(f, ref) <= 1e-12
+
+
+def test_guo_fp32_shifted_within_fp32_bounds():
+    fl = sc_inputs.drop(64, 64, 1, radius=16, seed=1)
+    say("guo fp32_shifted 64^2, 100 steps")
+    lat, f = gpu_run(9, fl.rho_A, fl.rho_B, 1.0, 1.0, 1.3, 100, precision="fp32_shifted",
+                     forcing="guo")
+    lat.close()
+    ref = oracle_run(9, fl.rho_A, fl.rho_B, 1.0, 1.0, 1.3, 100, forcing="guo")
+    assert maxabs(f, ref) <= 2e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_shifted"])
+def test_guo_variants_agree_bitwise(precision):
+    fl = sc_inputs.drop(40, 36, 30, radius=8, seed=3)
+    ref = None
+    for k in [(0, 64, 4, 8), (0, 32, 8, 3), (1, 64, 4, 4), (2, 64, 4, 8), (3, 32, 16, 6)]:
+        say(f"guo variants {precision} kernel {k}")
+        lat, f = gpu_run(19, fl.rho_A, fl.rho_B, 0.9, 1.1, 1.4, 30, precision=precision,
+                         kernel=k, body_A=2e-6, forcing="guo")
+        lat.close()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f, ref), k
+
+
+@pytest.mark.parametrize("mode", ["fused", "persistent"])
+def test_batch_mixing_both_schemes_equals_solo(mode):
+    from paper_1112_5547_amd import Batch, Lattice
+    specs = [(9, 64, 64, 1, "guo", 40), (9, 64, 64, 1, "shift", 40), (19, 20, 20, 20, "guo", 33)]
+
+    def make(spec, seed):
+        q, nx, ny, nz, forcing, _ = spec
+        fl = sc_inputs.drop(nx, ny, nz, radius=min(nx, ny) / 4, seed=seed)
+        lat = Lattice(q, nx, ny, nz, tau_A=0.8, tau_B=1.0, G=1.4, precision="fp32_shifted",
+                      forcing=forcing)
+        lat.init(fl.rho_A, fl.rho_B)
+        return lat
+
+    solo = []
+    for k, spec in enumerate(specs):
+        say(f"solo {spec}")
+        lat = make(spec, 40 + k)
+        lat.step(spec[5])
+        solo.append(lat.get_populations())
+        lat.close()
+    say(f"batch {mode} of both schemes")
+    b = Batch()
+    lats = [make(spec, 40 + k) for k, spec in enumerate(specs)]
+    for lat, spec in zip(lats, specs):
+        assert b.add(lat, spec[5])
+    for _ in range(8):
+        b.run(16, mode)
+        if len(b.poll()) == len(lats):
+            break
+    for lat, spec, ref in zip(lats, specs, solo):
+        b.remove(lat)
+        assert np.array_equal(lat.get_populations(), ref), spec
+        lat.close()
+    b.close()
+
+
+def test_shift_separates_where_guo_is_stable():
+    """tau = 0.55, rho = 1, G = 0.3 on a 256^2 lattice with +-1e-4 noise:
+    rho g^(tau) = 3.3 (spinodal under the velocity shift), rho G = 0.3 (stable
+    under Guo forcing).  After 3000 steps the shift scheme's order parameter
+    has grown to O(0.1) while Guo's noise has decayed."""
+    fl = sc_inputs.spinodal(256, 256, 1, rho0=0.5, noise=1e-4, seed=9)
+    start = float(np.abs(fl.rho_A - fl.rho_B).max())
+    spread = {}
+    for scheme in ("shift", "guo"):
+        say(f"stability contrast {scheme}")
+        lat, _ = gpu_run(9, fl.rho_A, fl.rho_B, 0.55, 0.55, 0.3, 3000, forcing=scheme)
+        rA, rB, _, T = lat.moments()
+        lat.close()
+        assert T["n_nonfinite"] == 0
+        spread[scheme] = float(np.abs(rA - rB).max())
+    assert spread["shift"] > 0.05 and spread["shift"] > 100 * start
+    assert spread["guo"] < 0.5 * start
