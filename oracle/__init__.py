@@ -64,11 +64,11 @@ def lib():
         L.oracle_init.argtypes = [i, i, i, i, dp, dp, dp, dp]
         L.oracle_moments.argtypes = [i, i, i, i, dp, dp, dp]
         L.oracle_force.argtypes = [i, i, i, i, d, dp, dp]
-        L.oracle_collide.argtypes = [i, i, i, i, d, d, d, d, dp, dp, i]
+        L.oracle_collide.argtypes = [i, i, i, i, d, d, d, d, dp, dp, i, d, d]
         L.oracle_stream.argtypes = [i, i, i, i, dp, dp]
-        L.oracle_run.argtypes = [i, i, i, i, d, d, d, d, dp, i, i]
+        L.oracle_run.argtypes = [i, i, i, i, d, d, d, d, dp, i, i, d, d]
         L.oracle_observables.argtypes = [i, i, i, i, d, d, d, d, dp, dp, dp, dp, dp, dp]
-        L.oracle_step_sites.argtypes = [i, i, i, i, d, d, d, d, dp, lp, i, dp, i]
+        L.oracle_step_sites.argtypes = [i, i, i, i, d, d, d, d, dp, lp, i, dp, i, d, d]
         for fn in ("oracle_lattice", "oracle_feq", "oracle_init", "oracle_moments",
                    "oracle_force", "oracle_collide", "oracle_stream", "oracle_run",
                    "oracle_observables", "oracle_step_sites"):
@@ -150,16 +150,25 @@ def _forcing(name: str) -> int:
     return FORCING[name]
 
 
+def _taum(tau_minus) -> tuple:
+    """(tau-_A, tau-_B); None or values <= 0 mean "equal to tau_s" (BGK)."""
+    if tau_minus is None:
+        return 0.0, 0.0
+    return float(tau_minus[0]), float(tau_minus[1])
+
+
 def collide(f: np.ndarray, tau_A: float, tau_B: float, G: float, body_A: float = 0.0,
-            forcing: str = "shift"):
+            forcing: str = "shift", tau_minus=None):
     """One collision of both species; forcing "shift" is the paper's velocity
-    shift (Sec. 2.1), "guo" the discrete forcing it cites (Sec. 2.3)."""
+    shift (Sec. 2.1), "guo" the discrete forcing it cites (Sec. 2.3);
+    tau_minus = (tau-_A, tau-_B) relaxes the odd moments separately (two
+    relaxation times)."""
     q = f.shape[1]
     nx, ny, nz = _dims(f.shape[2:])
     f = np.ascontiguousarray(f)
     out = np.zeros_like(f)
     _check(lib().oracle_collide(q, nx, ny, nz, tau_A, tau_B, G, body_A, _p(f), _p(out),
-                                _forcing(forcing)), "collide")
+                                _forcing(forcing), *_taum(tau_minus)), "collide")
     return out
 
 
@@ -173,13 +182,13 @@ def stream(fpost: np.ndarray) -> np.ndarray:
 
 
 def run(f: np.ndarray, tau_A: float, tau_B: float, G: float, steps: int,
-        body_A: float = 0.0, forcing: str = "shift") -> np.ndarray:
+        body_A: float = 0.0, forcing: str = "shift", tau_minus=None) -> np.ndarray:
     """``steps`` full collide+stream steps; returns a new array."""
     q = f.shape[1]
     nx, ny, nz = _dims(f.shape[2:])
     g = np.array(f, dtype=np.float64, order="C", copy=True)
     _check(lib().oracle_run(q, nx, ny, nz, tau_A, tau_B, G, body_A, _p(g), steps,
-                            _forcing(forcing)), "run")
+                            _forcing(forcing), *_taum(tau_minus)), "run")
     return g
 
 
@@ -201,7 +210,7 @@ def observables(f: np.ndarray, tau_A: float, tau_B: float, G: float, probe=None,
 
 
 def step_sites(f: np.ndarray, tau_A: float, tau_B: float, G: float, sites: np.ndarray,
-               body_A: float = 0.0, forcing: str = "shift") -> np.ndarray:
+               body_A: float = 0.0, forcing: str = "shift", tau_minus=None) -> np.ndarray:
     """Populations after one step at the given flat site indices: out[k, s, i]."""
     q = f.shape[1]
     nx, ny, nz = _dims(f.shape[2:])
@@ -210,5 +219,6 @@ def step_sites(f: np.ndarray, tau_A: float, tau_B: float, G: float, sites: np.nd
     _check(lib().oracle_step_sites(q, nx, ny, nz, tau_A, tau_B, G, body_A,
                                    _p(np.ascontiguousarray(f)),
                                    sites.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
-                                   len(sites), _p(out), _forcing(forcing)), "step_sites")
+                                   len(sites), _p(out), _forcing(forcing), *_taum(tau_minus)),
+           "step_sites")
     return out

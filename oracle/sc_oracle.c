@@ -27,7 +27,9 @@
  * paper's chemical potential, the worked example's bulk order parameter and
  * Laplace-law linearity; for the Guo forcing option: exact mass and
  * momentum balance, the laminar Kolmogorov profile, and the linearised growth
- * rate with the bare coupling g in place of g^(tau)), and cross-checked
+ * rate with the bare coupling g in place of g^(tau); for two relaxation
+ * times: the BGK limit, nu from the even and D from the odd relaxation time,
+ * the linearised update and its growth-rate limit), and cross-checked
  * against an independent NumPy implementation on small grids.
  */
 #include <math.h>
@@ -236,6 +238,76 @@ static double guo_source(const lat_t *L, int i, const double u[3], const double 
     return (1.0 - 1.0 / (2.0 * tau)) * L->w[i] * ((cF - uF) / CS2 + cu * cF / (CS2 * CS2));
 }
 
+/* Index of the velocity opposite to c_i. */
+static int opposite(const lat_t *L, int i) {
+    for (int k = 0; k < L->q; ++k)
+        if (L->c[k][0] == -L->c[i][0] && L->c[k][1] == -L->c[i][1] && L->c[k][2] == -L->c[i][2])
+            return k;
+    return i;
+}
+
+/* Collision of the populations fin[s*Q + i] of one site into fout, given the
+ * moments rho_s, j_s and the total force F_s (body force included) of both
+ * species.
+ *
+ * taup_s is the BGK relaxation time tau_s of eq:be.  taum_s is the relaxation
+ * time of the odd (antisymmetric) part of the populations: equal to taup_s
+ * the collision is the paper's BGK; different, it is the two-relaxation-time
+ * member of the multiple-relaxation-time family the paper cites (Sec. 2.1,
+ * last paragraph) for decoupling the diffusive and viscous time scales:
+ *   f*_i = f_i - (f+_i - feq+_i) / taup - (f-_i - feq-_i) / taum,
+ *   f+-_i = (f_i +- f_ibar) / 2,  ibar the velocity opposite to i.
+ * The odd moments carry the species momenta, so the momentum exchange and the
+ * force shift use taum: u' = sum_s j_s / taum_s / sum_s rho_s / taum_s and
+ * v_s = u' + taum_s F_s / rho_s.  The even moments carry the stress, so the
+ * viscosity is c_S^2 (taup - 1/2) and the interdiffusion c_S^2 (taum - 1/2).
+ * With Guo forcing the source splits likewise: its even part
+ * w_i [9 (c_i.u)(c_i.F_s) - 3 u.F_s] takes (1 - 1/(2 taup)), its odd part
+ * w_i 3 c_i.F_s takes (1 - 1/(2 taum)). */
+static void collide_site(const lat_t *L, const double rho[2], const double j[2][3],
+                         const double F[2][3], const double taup[2], const double taum[2],
+                         int forcing, const double *fin, double *fout) {
+    const int q = L->q;
+    double u[3], num[3] = {0.0, 0.0, 0.0}, den = 0.0;
+    for (int s = 0; s < 2; ++s) {
+        for (int a = 0; a < 3; ++a)
+            num[a] += (forcing == ORACLE_FORCING_GUO ? j[s][a] + 0.5 * F[s][a] : j[s][a]) / taum[s];
+        den += rho[s] / taum[s];
+    }
+    for (int a = 0; a < 3; ++a) u[a] = num[a] / den;
+    for (int s = 0; s < 2; ++s) {
+        double v[3], feq[19];
+        for (int a = 0; a < 3; ++a)
+            v[a] = forcing == ORACLE_FORCING_GUO ? u[a] : u[a] + taum[s] * F[s][a] / rho[s];
+        feq_at(L, rho[s], v, feq);
+        for (int i = 0; i < q; ++i) {
+            double fi = fin[s * q + i], out;
+            if (taum[s] == taup[s]) {
+                out = fi - (fi - feq[i]) / taup[s];
+                if (forcing == ORACLE_FORCING_GUO) out += guo_source(L, i, u, F[s], taup[s]);
+            } else {
+                int ib = opposite(L, i);
+                double fb = fin[s * q + ib];
+                double fp = 0.5 * (fi + fb), fm = 0.5 * (fi - fb);
+                double ep = 0.5 * (feq[i] + feq[ib]), em = 0.5 * (feq[i] - feq[ib]);
+                out = fi - (fp - ep) / taup[s] - (fm - em) / taum[s];
+                if (forcing == ORACLE_FORCING_GUO) {
+                    double cu = 0.0, cF = 0.0, uF = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        cu += L->c[i][a] * u[a];
+                        cF += L->c[i][a] * F[s][a];
+                        uF += u[a] * F[s][a];
+                    }
+                    double even = L->w[i] * (cu * cF / (CS2 * CS2) - uF / CS2);
+                    double odd = L->w[i] * cF / CS2;
+                    out += (1.0 - 1.0 / (2.0 * taup[s])) * even + (1.0 - 1.0 / (2.0 * taum[s])) * odd;
+                }
+            }
+            fout[s * q + i] = out;
+        }
+    }
+}
+
 /* One BGK collision of both species (eq:be, right-hand side).  Velocity
  * shift (the paper's scheme):
  *   u    = sum_s (1/tau_s) j_s / sum_s (1/tau_s) rho_s       (common velocity)
@@ -243,7 +315,8 @@ static double guo_source(const lat_t *L, int i, const double u[3], const double 
  *   f*_is = f_is - (f_is - f_is^eq(rho_s, v_s)) / tau_s;
  * Guo forcing as described above.  fpost may not alias f. */
 int oracle_collide(int q, int nx, int ny, int nz, double tauA, double tauB, double G,
-                   double bodyA, const double *f, double *fpost, int forcing) {
+                   double bodyA, const double *f, double *fpost, int forcing, double tmA,
+                   double tmB) {
     lat_t L;
     if (lat_make(&L, q, nx, ny, nz) != 0) return -1;
     double *rho = malloc(sizeof(double) * 2 * L.n);
@@ -257,52 +330,26 @@ int oracle_collide(int q, int nx, int ny, int nz, double tauA, double tauB, doub
     }
     oracle_moments(q, nx, ny, nz, f, rho, j);
     oracle_force(q, nx, ny, nz, G, rho, F); /* psi_s = rho_s */
-    const double tau[2] = {tauA, tauB};
-    double feq[19];
+    const double taup[2] = {tauA, tauB};
+    const double taum[2] = {tmA > 0.0 ? tmA : tauA, tmB > 0.0 ? tmB : tauB};
+    double fin[38], fout[38];
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long site = ((long)z * ny + y) * nx + x;
-                if (forcing == ORACLE_FORCING_GUO) {
-                    double Fs[2][3], num[3] = {0.0, 0.0, 0.0}, den = 0.0;
-                    for (int s = 0; s < 2; ++s) {
-                        double r = rho[s * L.n + site];
-                        for (int a = 0; a < 3; ++a) Fs[s][a] = F[(s * 3 + a) * L.n + site];
-                        if (bodyA != 0.0) Fs[s][0] += r * kolmogorov(bodyA, y, ny);
-                        for (int a = 0; a < 3; ++a)
-                            num[a] += (j[(s * 3 + a) * L.n + site] + 0.5 * Fs[s][a]) / tau[s];
-                        den += r / tau[s];
-                    }
-                    double u[3] = {num[0] / den, num[1] / den, num[2] / den};
-                    for (int s = 0; s < 2; ++s) {
-                        feq_at(&L, rho[s * L.n + site], u, feq);
-                        for (int i = 0; i < q; ++i) {
-                            double fi = f[fidx(&L, s, i, site)];
-                            fpost[fidx(&L, s, i, site)] =
-                                fi - (fi - feq[i]) / tau[s] + guo_source(&L, i, u, Fs[s], tau[s]);
-                        }
-                    }
-                    continue;
-                }
-                double num[3] = {0.0, 0.0, 0.0}, den = 0.0;
+                double r[2], js[2][3], Fs[2][3];
                 for (int s = 0; s < 2; ++s) {
-                    for (int a = 0; a < 3; ++a) num[a] += j[(s * 3 + a) * L.n + site] / tau[s];
-                    den += rho[s * L.n + site] / tau[s];
-                }
-                double u[3] = {num[0] / den, num[1] / den, num[2] / den};
-                for (int s = 0; s < 2; ++s) {
-                    double r = rho[s * L.n + site];
-                    double Fs[3];
-                    for (int a = 0; a < 3; ++a) Fs[a] = F[(s * 3 + a) * L.n + site];
-                    if (bodyA != 0.0) Fs[0] += r * kolmogorov(bodyA, y, ny);
-                    double v[3];
-                    for (int a = 0; a < 3; ++a) v[a] = u[a] + tau[s] * Fs[a] / r;
-                    feq_at(&L, r, v, feq);
-                    for (int i = 0; i < q; ++i) {
-                        double fi = f[fidx(&L, s, i, site)];
-                        fpost[fidx(&L, s, i, site)] = fi - (fi - feq[i]) / tau[s];
+                    r[s] = rho[s * L.n + site];
+                    for (int a = 0; a < 3; ++a) {
+                        js[s][a] = j[(s * 3 + a) * L.n + site];
+                        Fs[s][a] = F[(s * 3 + a) * L.n + site];
                     }
+                    if (bodyA != 0.0) Fs[s][0] += r[s] * kolmogorov(bodyA, y, ny);
+                    for (int i = 0; i < q; ++i) fin[s * q + i] = f[fidx(&L, s, i, site)];
                 }
+                collide_site(&L, r, js, Fs, taup, taum, forcing, fin, fout);
+                for (int s = 0; s < 2; ++s)
+                    for (int i = 0; i < q; ++i) fpost[fidx(&L, s, i, site)] = fout[s * q + i];
             }
     free(rho);
     free(j);
@@ -329,13 +376,13 @@ int oracle_stream(int q, int nx, int ny, int nz, const double *fpost, double *fn
 
 /* nsteps full time steps (collide, then stream), in place on f. */
 int oracle_run(int q, int nx, int ny, int nz, double tauA, double tauB, double G,
-               double bodyA, double *f, int nsteps, int forcing) {
+               double bodyA, double *f, int nsteps, int forcing, double tmA, double tmB) {
     lat_t L;
     if (lat_make(&L, q, nx, ny, nz) != 0 || nsteps < 0) return -1;
     double *tmp = malloc(sizeof(double) * 2 * q * L.n);
     if (!tmp) return -2;
     for (int t = 0; t < nsteps; ++t) {
-        oracle_collide(q, nx, ny, nz, tauA, tauB, G, bodyA, f, tmp, forcing);
+        oracle_collide(q, nx, ny, nz, tauA, tauB, G, bodyA, f, tmp, forcing, tmA, tmB);
         oracle_stream(q, nx, ny, nz, tmp, f);
     }
     free(tmp);
@@ -465,11 +512,12 @@ int oracle_observables(int q, int nx, int ny, int nz, double tauA, double tauB, 
  * lattices where a full oracle step is too slow to run in a test. */
 int oracle_step_sites(int q, int nx, int ny, int nz, double tauA, double tauB, double G,
                       double bodyA, const double *f, const long *sites, int nsites,
-                      double *out, int forcing) {
+                      double *out, int forcing, double tmA, double tmB) {
     lat_t L;
     if (lat_make(&L, q, nx, ny, nz) != 0) return -1;
-    const double tau[2] = {tauA, tauB};
-    double feq[19];
+    const double taup[2] = {tauA, tauB};
+    const double taum[2] = {tmA > 0.0 ? tmA : tauA, tmB > 0.0 ? tmB : tauB};
+    double fin[38], fout[38];
     for (int k = 0; k < nsites; ++k) {
         long site = sites[k];
         if (site < 0 || site >= L.n) return -1;
@@ -487,6 +535,7 @@ int oracle_step_sites(int q, int nx, int ny, int nz, double tauA, double tauB, d
                     double fv = f[fidx(&L, s, k2, up)];
                     rho[s] += fv;
                     for (int a = 0; a < 3; ++a) j[s][a] += fv * L.c[k2][a];
+                    fin[s * q + k2] = fv;
                 }
             }
             double Fs[2][3];
@@ -502,33 +551,8 @@ int oracle_step_sites(int q, int nx, int ny, int nz, double tauA, double tauB, d
                 for (int a = 0; a < 3; ++a) Fs[s][a] = -G * rho[s] * sum[a];
                 if (bodyA != 0.0) Fs[s][0] += rho[s] * kolmogorov(bodyA, y0, ny);
             }
-            if (forcing == ORACLE_FORCING_GUO) {
-                double num[3] = {0.0, 0.0, 0.0}, den = 0.0;
-                for (int s = 0; s < 2; ++s) {
-                    for (int a = 0; a < 3; ++a) num[a] += (j[s][a] + 0.5 * Fs[s][a]) / tau[s];
-                    den += rho[s] / tau[s];
-                }
-                double u[3] = {num[0] / den, num[1] / den, num[2] / den};
-                for (int s = 0; s < 2; ++s) {
-                    feq_at(&L, rho[s], u, feq);
-                    double fi = f[fidx(&L, s, i, up)];
-                    out[(long)k * 2 * q + s * q + i] =
-                        fi - (fi - feq[i]) / tau[s] + guo_source(&L, i, u, Fs[s], tau[s]);
-                }
-                continue;
-            }
-            double num[3] = {0.0, 0.0, 0.0}, den = 0.0;
-            for (int s = 0; s < 2; ++s) {
-                for (int a = 0; a < 3; ++a) num[a] += j[s][a] / tau[s];
-                den += rho[s] / tau[s];
-            }
-            for (int s = 0; s < 2; ++s) {
-                double v[3];
-                for (int a = 0; a < 3; ++a) v[a] = num[a] / den + tau[s] * Fs[s][a] / rho[s];
-                feq_at(&L, rho[s], v, feq);
-                double fi = f[fidx(&L, s, i, up)];
-                out[(long)k * 2 * q + s * q + i] = fi - (fi - feq[i]) / tau[s];
-            }
+            collide_site(&L, rho, j, Fs, taup, taum, forcing, fin, fout);
+            for (int s = 0; s < 2; ++s) out[(long)k * 2 * q + s * q + i] = fout[s * q + i];
         }
     }
     return 0;

@@ -54,8 +54,23 @@ def _shift(a: np.ndarray, c) -> np.ndarray:
     return np.roll(a, shift=(-int(c[2]), -int(c[1]), -int(c[0])), axis=(-3, -2, -1))
 
 
+def _opposite(c: np.ndarray) -> np.ndarray:
+    """Index of the opposite velocity, found by matching -c_i (vectorised)."""
+    match = (c[:, None, :] == -c[None, :, :]).all(axis=2)
+    return match.argmax(axis=1)
+
+
+def _relax(fs, fe, tp, tm, op):
+    """BGK when tp == tm, else even / odd parts relaxed with tp / tm."""
+    if tp == tm:
+        return fs - (fs - fe) / tp
+    fp, fm = 0.5 * (fs + fs[op]), 0.5 * (fs - fs[op])
+    ep, em = 0.5 * (fe + fe[op]), 0.5 * (fe - fe[op])
+    return fs - (fp - ep) / tp - (fm - em) / tm
+
+
 def step(f: np.ndarray, tau_A: float, tau_B: float, G: float, body_A: float = 0.0,
-         forcing: str = "shift"):
+         forcing: str = "shift", tau_minus=None):
     q = f.shape[1]
     c, w = velocity_set(q)
     cf = c.astype(np.float64)
@@ -73,27 +88,34 @@ def step(f: np.ndarray, tau_A: float, tau_B: float, G: float, body_A: float = 0.
         y = np.arange(ny, dtype=np.float64).reshape(1, ny, 1)
         F[:, 0] += rho * body_A * np.sin(2.0 * np.pi * y / ny)
     tau = np.array([tau_A, tau_B])
+    tm = tau.copy() if tau_minus is None else np.array(
+        [tm_ if tm_ > 0 else t_ for tm_, t_ in zip(tau_minus, tau)], dtype=np.float64)
+    op = _opposite(c)
     out = np.empty_like(f)
     if forcing == "guo":
         # equilibrium at the common velocity of the half-force corrected momenta,
-        # plus each species' discrete forcing term (Hermite projection of F_s)
-        u = ((j + 0.5 * F) / tau[:, None, None, None, None]).sum(0) / \
-            (rho / tau[:, None, None, None]).sum(0)
+        # plus each species' discrete forcing term (Hermite projection of F_s),
+        # its odd part (c.F) scaled with the odd relaxation time
+        u = ((j + 0.5 * F) / tm[:, None, None, None, None]).sum(0) / \
+            (rho / tm[:, None, None, None]).sum(0)
         cu = np.einsum("ia,azyx->izyx", cf, u)
+        ww = w.reshape(-1, 1, 1, 1)
         for s in range(2):
             cF = np.einsum("ia,azyx->izyx", cf, F[s])
             uF = (u * F[s]).sum(0)
-            src = w.reshape(-1, 1, 1, 1) * ((cF - uF[None]) / CS2 + cu * cF / CS2**2)
-            fs = f[s] - (f[s] - equilibrium(q, rho[s], u)) / tau[s] + (1 - 0.5 / tau[s]) * src
+            even = ww * (cu * cF / CS2**2 - uF[None] / CS2)
+            odd = ww * cF / CS2
+            fs = _relax(f[s], equilibrium(q, rho[s], u), tau[s], tm[s], op)
+            fs = fs + (1 - 0.5 / tau[s]) * even + (1 - 0.5 / tm[s]) * odd
             for i in range(q):
                 out[s, i] = np.roll(fs[i], shift=(int(c[i, 2]), int(c[i, 1]), int(c[i, 0])),
                                     axis=(-3, -2, -1))
         return out
-    u = (j / tau[:, None, None, None, None]).sum(0) / (rho / tau[:, None, None, None]).sum(0)
+    u = (j / tm[:, None, None, None, None]).sum(0) / (rho / tm[:, None, None, None]).sum(0)
     for s in range(2):
-        v = u + tau[s] * F[s] / rho[s]
+        v = u + tm[s] * F[s] / rho[s]
         fe = equilibrium(q, rho[s], v)
-        fs = f[s] - (f[s] - fe) / tau[s]
+        fs = _relax(f[s], fe, tau[s], tm[s], op)
         for i in range(q):
             out[s, i] = np.roll(fs[i], shift=(int(c[i, 2]), int(c[i, 1]), int(c[i, 0])),
                                 axis=(-3, -2, -1))
@@ -101,8 +123,8 @@ def step(f: np.ndarray, tau_A: float, tau_B: float, G: float, body_A: float = 0.
 
 
 def run(f: np.ndarray, tau_A: float, tau_B: float, G: float, steps: int,
-        body_A: float = 0.0, forcing: str = "shift") -> np.ndarray:
+        body_A: float = 0.0, forcing: str = "shift", tau_minus=None) -> np.ndarray:
     g = np.array(f, dtype=np.float64, copy=True)
     for _ in range(steps):
-        g = step(g, tau_A, tau_B, G, body_A, forcing)
+        g = step(g, tau_A, tau_B, G, body_A, forcing, tau_minus)
     return g

@@ -39,18 +39,28 @@ def vset(q):
 
 
 def update_matrix(q: int, k, rho_A0: float, rho_B0: float, tau_A: float, tau_B: float,
-                  G: float, forcing: str = "shift") -> np.ndarray:
+                  G: float, forcing: str = "shift", tau_minus=None) -> np.ndarray:
     """The 2Q x 2Q complex matrix M(k) acting on fhat[s*Q + i].
 
     forcing "guo" linearises the discrete forcing instead of the velocity
     shift: du = sum_s (dj_s + dF_s / 2) / tau_s / sum_s rho_s0 / tau_s, the
     equilibrium at du for every species, plus the source
-    (1 - 1/(2 tau_s)) w_i c_i.dF_s / c_S^2 (its terms in u vanish at rest)."""
+    (1 - 1/(2 tau_s)) w_i c_i.dF_s / c_S^2 (its terms in u vanish at rest).
+
+    tau_minus = (tm_A, tm_B) relaxes the odd part of each species' deviation
+    from equilibrium with tm_s (two relaxation times): the collision acts on
+    d = fhat - dfeq as d - P+ d / tau_s - P- d / tm_s, P+- the projections on
+    the parts even / odd under c_i -> -c_i; the momentum weights, the force
+    shift and the source (all odd) take tm_s."""
     c, w = vset(q)
     k = np.asarray(k, dtype=np.float64)
     phase = np.exp(1j * (c @ k))                       # e^{i k.c_i}
     rho0 = np.array([rho_A0, rho_B0])
     tau = np.array([tau_A, tau_B])
+    tm = tau if tau_minus is None else np.array(tau_minus, dtype=np.float64)
+    # projections on the even / odd parts under velocity reversal
+    rev = np.array([[1.0 if np.all(c[a] == -c[b]) else 0.0 for b in range(q)] for a in range(q)])
+    Pe, Po = 0.5 * (np.eye(q) + rev), 0.5 * (np.eye(q) - rev)
     n = 2 * q
     M = np.zeros((n, n), dtype=complex)
     gvec = (w[:, None] * c * phase[:, None]).sum(0)    # sum_i w_i c_i e^{ik.c_i}
@@ -63,31 +73,35 @@ def update_matrix(q: int, k, rho_A0: float, rho_B0: float, tau_A: float, tau_B: 
         dF = -G * rho0[:, None] * dgath
         out = np.zeros((2, q), dtype=complex)
         if forcing == "guo":
-            du = ((dj + 0.5 * dF) / tau[:, None]).sum(0) / (rho0 / tau).sum()
+            du = ((dj + 0.5 * dF) / tm[:, None]).sum(0) / (rho0 / tm).sum()
             for s in range(2):
                 dfeq = w * (drho[s] + rho0[s] * (c @ du) / CS2)
-                dsrc = (1.0 - 0.5 / tau[s]) * w * (c @ dF[s]) / CS2
-                out[s] = np.conj(phase) * ((1.0 - 1.0 / tau[s]) * fh[s] + dfeq / tau[s] + dsrc)
+                dsrc = (1.0 - 0.5 / tm[s]) * w * (c @ dF[s]) / CS2
+                d = fh[s] - dfeq
+                dfs = fh[s] - Pe @ d / tau[s] - Po @ d / tm[s] + dsrc
+                out[s] = np.conj(phase) * dfs
             M[:, col] = out.reshape(-1)
             continue
-        du = (dj / tau[:, None]).sum(0) / (rho0 / tau).sum()
+        du = (dj / tm[:, None]).sum(0) / (rho0 / tm).sum()
         for s in range(2):
-            dv = du + tau[s] * dF[s] / rho0[s]
+            dv = du + tm[s] * dF[s] / rho0[s]
             dfeq = w * (drho[s] + rho0[s] * (c @ dv) / CS2)
-            dfs = (1.0 - 1.0 / tau[s]) * fh[s] + dfeq / tau[s]
+            d = fh[s] - dfeq
+            dfs = fh[s] - Pe @ d / tau[s] - Po @ d / tm[s]
             out[s] = np.conj(phase) * dfs
         M[:, col] = out.reshape(-1)
     return M
 
 
-def phi_mode_rate(q, k, rho, tau, G, forcing: str = "shift"):
+def phi_mode_rate(q, k, rho, tau, G, forcing: str = "shift", tau_minus=None):
     """Growth rate log(lambda) of the order-parameter mode at wavevector k.
 
     Base state rho_A0 = rho_B0 = rho/2; the phi mode is the eigenvector whose
     density perturbation is antisymmetric (drho_A = -drho_B) with the
     eigenvalue closest to 1.
     """
-    M = update_matrix(q, k, rho / 2, rho / 2, tau, tau, G, forcing)
+    M = update_matrix(q, k, rho / 2, rho / 2, tau, tau, G, forcing,
+                      None if tau_minus is None else (tau_minus, tau_minus))
     lam, vec = np.linalg.eig(M)
     best = None
     for j in range(len(lam)):
