@@ -95,12 +95,14 @@ def traffic_for(kernel_name: str, kernel_ms: float):
     return b / (kernel_ms * 1e-3) / 1e9, b
 
 
-def kernel_symbol(kern, precision: str, forcing: str = "shift") -> str:
+def kernel_symbol(kern, precision: str, forcing: str = "shift", trt: bool = False) -> str:
     variant, tx, ty, _ = kern
     name = {0: "k_step_fused", 2: "k_step_pipe", 3: "k_step_repull"}.get(variant, "k_collide2")
     pr = "sc::PF64" if precision == "fp64" else "sc::PF32S"
     if forcing == "guo":
         pr += "G"
+    if trt:
+        pr += "T"
     if variant == 1:
         return f"sc::k_collide2<19, {pr}>"
     return f"sc::{name}<19, {pr}, {tx}, {ty}>"
@@ -111,10 +113,11 @@ def b_alg(q: int, esize: int) -> int:
     return 2 * q * 2 * esize
 
 
-def time_lattice(fields, precision, steps, warmup, kernel=None, forcing="shift"):
+def time_lattice(fields, precision, steps, warmup, kernel=None, forcing="shift", tau_minus=None):
     import torch
     from paper_1112_5547_amd import Lattice, autotune
-    lat = Lattice(Q19, L, L, L, tau_A=TAU, tau_B=TAU, G=G, precision=precision, forcing=forcing)
+    lat = Lattice(Q19, L, L, L, tau_A=TAU, tau_B=TAU, G=G, precision=precision, forcing=forcing,
+                  tau_minus=tau_minus)
     if kernel:
         lat.set_kernel(*kernel)
     else:
@@ -240,7 +243,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--no-guo", action="store_true", help="skip the Guo-forcing leg")
+    ap.add_argument("--no-schemes", action="store_true",
+                    help="skip the Guo-forcing and two-relaxation-time legs")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-lattices leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-jobs leg")
@@ -313,23 +317,28 @@ def main():
             "kernel": list(r32["kernel"]),
             "mass_drift_A": (r32["T"]["mass_A"] - r32["T0"]["mass_A"]) / r32["T0"]["mass_A"],
         }
-    if not args.no_guo:
-        # the same workload with the Guo discrete forcing (separate kernels)
-        out["guo"] = {}
-        for prec, esize in (("fp64", 8), ("fp32_shifted", 4)):
-            rg = time_lattice(fields, prec, args.steps, args.warmup, forcing="guo")
-            achg = b_alg(Q19, esize) * n / (rg["kernel_ms"] * 1e-3) / 1e9
-            out["guo"][prec] = {
-                "value": round(n * args.steps / rg["wall_s"] / 1e6, 1), "unit": "MLUPS",
-                "ms_per_step": round(rg["wall_s"] * 1e3 / args.steps, 4),
-                "roofline": {"bound": "hbm", "achieved": round(achg, 1), "peak": PEAK_HBM_GBPS,
-                             "unit": "GB/s", "frac": round(achg / PEAK_HBM_GBPS, 4),
-                             "kernel": kernel_symbol(rg["kernel"], prec, "guo"),
-                             "kernel_ms": round(rg["kernel_ms"], 4),
-                             "bytes_per_site": b_alg(Q19, esize)},
-                "kernel": list(rg["kernel"]),
-                "mass_drift_A": (rg["T"]["mass_A"] - rg["T0"]["mass_A"]) / rg["T0"]["mass_A"],
-            }
+    if not args.no_schemes:
+        # the same workload with the Guo discrete forcing and with two
+        # relaxation times (tau- = 0.8), each its own kernel instantiation
+        out["schemes"] = {}
+        for scheme, forcing, tm in (("guo", "guo", None), ("trt", "shift", (0.8, 0.8))):
+            out["schemes"][scheme] = {}
+            for prec, esize in (("fp64", 8), ("fp32_shifted", 4)):
+                rg = time_lattice(fields, prec, args.steps, args.warmup, forcing=forcing,
+                                  tau_minus=tm)
+                achg = b_alg(Q19, esize) * n / (rg["kernel_ms"] * 1e-3) / 1e9
+                out["schemes"][scheme][prec] = {
+                    "value": round(n * args.steps / rg["wall_s"] / 1e6, 1), "unit": "MLUPS",
+                    "ms_per_step": round(rg["wall_s"] * 1e3 / args.steps, 4),
+                    "roofline": {"bound": "hbm", "achieved": round(achg, 1),
+                                 "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                                 "frac": round(achg / PEAK_HBM_GBPS, 4),
+                                 "kernel": kernel_symbol(rg["kernel"], prec, forcing, tm is not None),
+                                 "kernel_ms": round(rg["kernel_ms"], 4),
+                                 "bytes_per_site": b_alg(Q19, esize)},
+                    "kernel": list(rg["kernel"]),
+                    "mass_drift_A": (rg["T"]["mass_A"] - rg["T0"]["mass_A"]) / rg["T0"]["mass_A"],
+                }
     if not args.no_batch:
         out["batched"] = batch_leg(64, args.batch_steps, epoch=250)
     if not args.no_serve:

@@ -100,7 +100,18 @@ enum {
  *   means "the volume mean of the densities passed to lbm_sc_init";
  *   body_A: amplitude A of the Kolmogorov body force of Sec. 4.2,
  *   F_x += rho_s A sin(2 pi y / ny) on each species (0 disables it);
- *   forcing: LBM_FORCING_SHIFT (default) or LBM_FORCING_GUO. */
+ *   forcing: LBM_FORCING_SHIFT (default) or LBM_FORCING_GUO;
+ *   tau_minus_A, tau_minus_B: relaxation time of the odd part (under
+ *   c_i -> -c_i) of each species' deviation from equilibrium, > 1/2; a value
+ *   <= 0 means tau_s (the paper's single-relaxation-time BGK, eq:be).  A
+ *   different value is the two-relaxation-time member of the
+ *   multiple-relaxation-time family the paper names for decoupling the
+ *   diffusive and viscous time scales (Sec. 2.1, closing remark):
+ *     f*_is = f_is - (f+_is - feq+_is) / tau_s - (f-_is - feq-_is) / tau-_s,
+ *     f+-_i = (f_i +- f_ibar) / 2 (ibar: the velocity opposite to i),
+ *   with the momentum weights and the force shift (or Guo's odd source part)
+ *   taken with tau-_s.  The viscosity is c_S^2 (tau_s - 1/2), the
+ *   interdiffusion c_S^2 (tau-_s - 1/2). */
 typedef struct {
     int lattice;
     int nx, ny, nz;
@@ -110,6 +121,7 @@ typedef struct {
     double rho_ref_A, rho_ref_B;
     double body_A;
     int forcing;
+    double tau_minus_A, tau_minus_B;
 } lbm_sc_params;
 
 /* FP64 totals of one state, all reduced on the GPU in a fixed order.
@@ -143,7 +155,7 @@ typedef struct {
 } lbm_sc_totals;
 
 /* Fills *p with FP64, no body force, automatic reference densities, the
- * velocity-shift forcing. */
+ * velocity-shift forcing and one relaxation time. */
 int lbm_sc_params_default(lbm_sc_params *p, int lattice, int nx, int ny, int nz,
                           double tau_A, double tau_B, double G);
 

@@ -31,6 +31,7 @@ class Params(ctypes.Structure):
         ("rho_ref_A", ctypes.c_double), ("rho_ref_B", ctypes.c_double),
         ("body_A", ctypes.c_double),
         ("forcing", ctypes.c_int),
+        ("tau_minus_A", ctypes.c_double), ("tau_minus_B", ctypes.c_double),
     ]
 
 

@@ -16,7 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm_sc.so")
-SOURCES = ["sc_kernels.hip", "sc_runtime.hip", "sc_batch.hip"]
+SOURCES = ["sc_kernels.hip", "sc_runtime.hip", "sc_batch.hip"] + [
+    f"sc_step_{p}.hip" for p in ("pf64", "pf32s", "pf64g", "pf32sg", "pf64t", "pf32st", "pf64gt",
+                                 "pf32sgt")]
 ARCH = os.environ.get("LBM_SC_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

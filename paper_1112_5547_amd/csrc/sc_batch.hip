@@ -24,156 +24,17 @@ using namespace sc;
 
 namespace {
 
-struct BatchDesc {
-    StepParams sp[2];  // parity 0 / 1 (source and destination swapped)
-    int Q;
-    int base_parity;   // buffer holding the state at epoch start
-    int steps;         // steps of this epoch
-    int pad;
-};
-
-struct WorkItem {
-    int member, tile_x, tile_y, chunk;
-};
-
-// sync words: [0] barrier count, [1] barrier generation, [2] timeout flag,
-// [3..3+K) per-step tile claim counters
-constexpr int SYNC_COUNT = 0, SYNC_GEN = 1, SYNC_TIMEOUT = 2, SYNC_CTR = 3;
-constexpr unsigned kSpinLimit = 1u << 26;  // ~seconds of s_sleep polling per barrier
-
-template <class PR, int NT, int TX19, int TY19>
-struct BatchTiles {
-    using T9 = TileStep<9, PR, NT, 1>;
-    using T19 = TileStep<19, PR, TX19, TY19>;
-    static_assert(TX19 * TY19 == NT, "both lattice types use the block size");
-    static constexpr int LDS_ELEMS =
-        T9::LDS_ELEMS > T19::LDS_ELEMS ? T9::LDS_ELEMS : T19::LDS_ELEMS;
-    __device__ static __forceinline__ void run(const BatchDesc& d, const WorkItem& w, int k,
-                               typename PR::A* lds) {
-        const int parity = d.base_parity ^ (k & 1);
-        if (d.Q == 9)
-            T9::run(d.sp[parity], w.tile_x, w.tile_y, w.chunk, lds);
-        else
-            T19::run(d.sp[parity], w.tile_x, w.tile_y, w.chunk, lds);
-    }
-};
-
-template <class PR>
-struct BatchWaves {
-    static constexpr int value = PR::shifted ? 3 : 2;
-};
-
-template <class PR, int NT, int TX19, int TY19>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<PR>::value)))
-k_batch_step(const BatchDesc* __restrict__ desc, const WorkItem* __restrict__ work, int nwork,
-             int k) {
-    using BT = BatchTiles<PR, NT, TX19, TY19>;
-    __shared__ typename PR::A lds[BT::LDS_ELEMS];
-    const int it = (int)blockIdx.x;
-    if (it >= nwork) return;
-    const WorkItem w = work[it];
-    const BatchDesc& d = desc[w.member];
-    if (k >= d.steps) return;
-    BT::run(d, w, k, lds);
-}
-
-__device__ __forceinline__ unsigned ld_acquire(unsigned* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Grid-wide barrier for co-resident blocks; returns false if the wait hit
-// the spin limit or another block already reported a timeout (all blocks
-// then leave the kernel, so every wave terminates).
-__device__ bool grid_barrier(unsigned* sync, unsigned nblocks, unsigned& gen, int* s_flag) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        const unsigned g = gen;
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&sync[SYNC_COUNT], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&sync[SYNC_COUNT], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sync[SYNC_GEN], g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned spins = 0;
-            while (ld_acquire(&sync[SYNC_GEN]) == g) {
-                if (ld_acquire(&sync[SYNC_TIMEOUT]) != 0u || ++spins > kSpinLimit) {
-                    __hip_atomic_store(&sync[SYNC_TIMEOUT], 1u, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-        }
-        gen = g + 1;
-        *s_flag = ok;
-    }
-    __syncthreads();
-    const bool ok = *s_flag != 0;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return ok;
-}
-
-template <class PR, int NT, int TX19, int TY19>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<PR>::value)))
-k_batch_persistent(const BatchDesc* __restrict__ desc, const WorkItem* __restrict__ work,
-                   int nwork, int ksteps, unsigned* sync) {
-    using BT = BatchTiles<PR, NT, TX19, TY19>;
-    __shared__ typename PR::A lds[BT::LDS_ELEMS];
-    __shared__ int s_item;
-    __shared__ int s_flag;
-    unsigned gen = 0;
-    for (int k = 0; k < ksteps; ++k) {
-        for (;;) {
-            if (threadIdx.x == 0)
-                s_item = (int)__hip_atomic_fetch_add(&sync[SYNC_CTR + k], 1u, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-            __syncthreads();
-            const int it = s_item;
-            __syncthreads();
-            if (it >= nwork) break;
-            const WorkItem w = work[it];
-            const BatchDesc& d = desc[w.member];
-            if (k < d.steps) BT::run(d, w, k, lds);
-        }
-        if (k + 1 < ksteps && !grid_barrier(sync, gridDim.x, gen, &s_flag)) return;
-    }
-}
-
+// Clears the claim counters of a persistent launch (a kernel, so that the
+// clear may sit inside a captured graph).
 __global__ void k_zero_u32(unsigned* p, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
-
-// --- launch table ------------------------------------------------------------
 
 struct BatchCfg {
     int nt, tx19, ty19;
 };
 static const BatchCfg kBatchCfgs[] = {{256, 64, 4}, {256, 32, 8}, {256, 16, 16}, {128, 32, 4},
                                       {512, 64, 8}, {512, 32, 16}};
-
-using StepFn = void (*)(const BatchDesc*, const WorkItem*, int, int);
-using PersFn = void (*)(const BatchDesc*, const WorkItem*, int, int, unsigned*);
-
-template <class PR>
-bool lookup_fns(int nt, int tx19, int ty19, StepFn* sf, PersFn* pf) {
-#define SC_CFG(NT_, X_, Y_)                                          \
-    if (nt == NT_ && tx19 == X_ && ty19 == Y_) {                     \
-        *sf = k_batch_step<PR, NT_, X_, Y_>;                         \
-        *pf = k_batch_persistent<PR, NT_, X_, Y_>;                   \
-        return true;                                                 \
-    }
-    SC_CFG(256, 64, 4)
-    SC_CFG(256, 32, 8)
-    SC_CFG(256, 16, 16)
-    SC_CFG(128, 32, 4)
-    SC_CFG(512, 64, 8)
-    SC_CFG(512, 32, 16)
-#undef SC_CFG
-    return false;
-}
 
 bool cfg_supported(int nt, int tx19, int ty19) {
     for (const BatchCfg& c : kBatchCfgs)
@@ -211,7 +72,7 @@ struct lbm_batch {
     std::vector<Member> members;
     int nt = 256, tx19 = 64, ty19 = 4;
     int mb9 = 0, mb19 = 0;  // 0: each member's own march chunk
-    Group grp[4];           // by step_policy: FP64, FP32-shifted, and their Guo forms
+    Group grp[kPolicies];   // one per kernel policy (precision, forcing, relaxation)
     int err = 0;
 };
 
@@ -336,12 +197,9 @@ int run_group(lbm_batch* b, int prec, const std::vector<int>& idx, const std::ve
                             hipMemcpyHostToDevice, b->stream));
     BCALL(b, hipEventRecord(g.staged, b->stream));
 
-    StepFn sf = nullptr;
-    PersFn pf = nullptr;
-    const bool ok = prec == 0   ? lookup_fns<PF64>(b->nt, b->tx19, b->ty19, &sf, &pf)
-                    : prec == 1 ? lookup_fns<PF32S>(b->nt, b->tx19, b->ty19, &sf, &pf)
-                    : prec == 2 ? lookup_fns<PF64G>(b->nt, b->tx19, b->ty19, &sf, &pf)
-                                : lookup_fns<PF32SG>(b->nt, b->tx19, b->ty19, &sf, &pf);
+    BatchStepFn sf = nullptr;
+    BatchPersFn pf = nullptr;
+    const bool ok = batch_kernels(prec, b->nt, b->tx19, b->ty19, &sf, &pf);
     if (!ok) return LBM_EINVAL;
 
     int grid = nwork;
@@ -463,17 +321,17 @@ int lbm_batch_run(lbm_batch* b, int epoch_steps, int mode) {
         return LBM_EINVAL;
     if (epoch_steps == 0) return LBM_OK;
     (void)hipSetDevice(b->device);
-    std::vector<int> idx[4], ks[4];
+    std::vector<int> idx[kPolicies], ks[kPolicies];
     for (size_t i = 0; i < b->members.size(); ++i) {
         Member& m = b->members[i];
         if (m.remaining <= 0 || m.h->err) continue;
         const int k = (int)std::min<long long>(m.remaining, epoch_steps);
-        const int prec = step_policy(m.h->p.precision, m.h->p.forcing);
+        const int prec = sc_policy(m.h->p);
         idx[prec].push_back((int)i);
         ks[prec].push_back(k);
     }
     if (mode == LBM_BATCH_PER_LATTICE) {
-        for (int prec = 0; prec < 4; ++prec)
+        for (int prec = 0; prec < kPolicies; ++prec)
             for (size_t m = 0; m < idx[prec].size(); ++m) {
                 lbm_sc* h = b->members[idx[prec][m]].h;
                 lbm_batch* keep = h->batch;
@@ -488,7 +346,7 @@ int lbm_batch_run(lbm_batch* b, int epoch_steps, int mode) {
             }
         return LBM_OK;
     }
-    for (int prec = 0; prec < 4; ++prec) {
+    for (int prec = 0; prec < kPolicies; ++prec) {
         if (idx[prec].empty()) continue;
         const int K = *std::max_element(ks[prec].begin(), ks[prec].end());
         const int rc = run_group(b, prec, idx[prec], ks[prec], K, mode);
@@ -509,7 +367,7 @@ int lbm_batch_poll(lbm_batch* b, lbm_sc** done, int max_done, int* n_done) {
     if (b->err) return b->err;
     (void)hipSetDevice(b->device);
     BCALL(b, hipStreamSynchronize(b->stream));
-    for (int prec = 0; prec < 4; ++prec) {
+    for (int prec = 0; prec < kPolicies; ++prec) {
         Group& g = b->grp[prec];
         if (g.d_sync && g.g_mode == LBM_BATCH_PERSISTENT) {
             unsigned flag = 0;

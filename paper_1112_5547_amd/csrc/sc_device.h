@@ -76,6 +76,16 @@ struct VSet<19> {
     }
 };
 
+// Index of the velocity opposite to c_i.
+template <int Q>
+__host__ __device__ constexpr int opposite(int i) {
+    for (int k = 0; k < Q; ++k)
+        if (VSet<Q>::cx(k) == -VSet<Q>::cx(i) && VSet<Q>::cy(k) == -VSet<Q>::cy(i) &&
+            VSet<Q>::cz(k) == -VSet<Q>::cz(i))
+            return k;
+    return i;
+}
+
 // Plane geometry: the march axis is the slowest lattice axis.  A velocity
 // moves (dx, dy) inside the plane and dm across planes.
 template <int Q>
@@ -99,6 +109,7 @@ struct PF64 {
     using A = double;
     static constexpr bool shifted = false;
     static constexpr bool guo = false;   // force through the velocity shift
+    static constexpr bool trt = false;   // one relaxation time (BGK)
     static constexpr int code = 0;
 };
 struct PF32S {
@@ -106,15 +117,29 @@ struct PF32S {
     using A = float;
     static constexpr bool shifted = true;
     static constexpr bool guo = false;
+    static constexpr bool trt = false;
     static constexpr int code = 1;
 };
-// The same storage with the Guo discrete forcing: the step kernels are
-// instantiated per forcing scheme, so neither pays for the other's registers.
+// The same storage with the Guo discrete forcing (G) and / or two relaxation
+// times (T).  The step kernels are instantiated per policy, so no scheme pays
+// for another's registers.
 struct PF64G : PF64 {
     static constexpr bool guo = true;
 };
 struct PF32SG : PF32S {
     static constexpr bool guo = true;
+};
+struct PF64T : PF64 {
+    static constexpr bool trt = true;
+};
+struct PF32ST : PF32S {
+    static constexpr bool trt = true;
+};
+struct PF64GT : PF64G {
+    static constexpr bool trt = true;
+};
+struct PF32SGT : PF32SG {
+    static constexpr bool trt = true;
 };
 
 // Everything a step of one lattice needs; passed by value into kernels or
@@ -129,6 +154,7 @@ struct StepParams {
     int nchunks, mb;    // march chunks of mb planes
     int ny_lat;         // lattice y extent (Kolmogorov forcing period)
     double tau[2], omega[2];
+    double tau_m[2], omega_m[2];  // odd-part relaxation (= tau, omega for one relaxation time)
     double G;
     double rho_ref[2];
     double body_A;
@@ -235,6 +261,8 @@ __device__ __forceinline__ StepParams uniform_params(const StepParams& q) {
     for (int s = 0; s < 2; ++s) {
         p.tau[s] = unid(q.tau[s]);
         p.omega[s] = unid(q.omega[s]);
+        p.tau_m[s] = unid(q.tau_m[s]);
+        p.omega_m[s] = unid(q.omega_m[s]);
         p.rho_ref[s] = unid(q.rho_ref[s]);
     }
     p.G = unid(q.G);
@@ -278,49 +306,50 @@ __device__ __forceinline__ void gather(Rho&& rho, A (&g)[2][3]) {
     }
 }
 
-// Collision of one site and store of its 2Q post-collision populations.
-//   f      : the site's pulled populations f_is(x, t) (shifted h_is in FP32 mode)
-//   g[s]   : sum_i w_i rho_s(x + c_i) c_i, the gather of species s
-//   body   : external acceleration along x (0 without forcing)
-// The force on species s is F_s = rho_s a_s with a_s = -G g[s'] + body x.
-// Velocity shift (p.forcing == 0, the paper's scheme): the equilibrium of s
-// is taken at v_s = u' + tau_s a_s, u' = sum_s j_s/tau_s / sum_s rho_s/tau_s.
-// Guo forcing (p.forcing == 1): both species' equilibria at the common
-// u = sum_s (j_s + F_s/2)/tau_s / sum_s rho_s/tau_s, plus the source
-// S_is = (1 - 1/(2 tau_s)) w_i [3 (c_i - u).F_s + 9 (c_i.u)(c_i.F_s)].
-// Stores f*_is at byte offset soff + voff of the (s, i) arrays of dst.  Every
-// launch form (fused, two-pass, batched, persistent) calls this function, so
-// the per-site arithmetic is identical across them.
-// Relaxation and store of species S at equilibrium velocity v; with GUO the
-// discrete forcing source of force F (u = v) is added.
-template <int Q, class PR, bool GUO>
+// Relaxation and store of species s towards its equilibrium at velocity v.
+//   om, omm : 1/tau_s of the even and of the odd part of the deviation from
+//             equilibrium (equal for one relaxation time)
+//   F       : the species' force, for the Guo source (u = v then)
+// One relaxation time: f*_i = f_i + om (feq_i - f_i) [+ Guo source].  Two
+// (PR::trt): the same plus (om - omm) / 2 [(f_i - f_ib) - (feq_i - feq_ib)]
+// with ib the opposite velocity, which relaxes the odd part with omm; the
+// pairs (i, ib) are processed together.  The Guo source's even part
+// w_i (9 cu cF - 3 u.F) takes (1 - om/2), its odd part w_i 3 cF (1 - omm/2).
+template <int Q, class PR>
 __device__ __forceinline__ void relax_store(const typename PR::T (&fs)[Q], int s,
                                             const typename PR::A (&v)[3],
                                             const typename PR::A (&F)[3], typename PR::A rho,
                                             typename PR::A rfull, typename PR::A om,
-                                            char* __restrict__ dst, uint32_t pbytes,
-                                            uint32_t voff, uint32_t soff) {
+                                            typename PR::A omm, char* __restrict__ dst,
+                                            uint32_t pbytes, uint32_t voff, uint32_t soff) {
     using T = typename PR::T;
     using A = typename PR::A;
     const A vv = fmaa(v[0], v[0], fmaa(v[1], v[1], v[2] * v[2]));
     const A base = fmaa(A(-1.5), vv, A(1));
-    // Guo source with the factor (1 - 1/(2 tau)) folded into the force:
-    // S_i = w_i [cF (9 cu + 3) - 3 u.F], F scaled
-    A Fp[3] = {A(0), A(0), A(0)}, uF3 = A(0);
-    if (GUO) {
-        const A pre = fmaa(A(-0.5), om, A(1));
+    // Guo source S_i = w_i [cF (c9 cu + c3) - uF3] with the prefactors folded
+    // into c9, c3 and uF3 (two relaxation times) or into the force (one)
+    A Fp[3] = {A(0), A(0), A(0)}, uF3 = A(0), c9 = A(9), c3 = A(3);
+    if constexpr (PR::guo) {
+        const A pe = fmaa(A(-0.5), om, A(1));
+        if constexpr (PR::trt) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) Fp[a] = pre * F[a];
-        uF3 = A(3) * fmaa(v[0], Fp[0], fmaa(v[1], Fp[1], v[2] * Fp[2]));
+            for (int a = 0; a < 3; ++a) Fp[a] = F[a];
+            c9 = A(9) * pe;
+            c3 = A(3) * fmaa(A(-0.5), omm, A(1));
+            uF3 = (A(3) * pe) * fmaa(v[0], Fp[0], fmaa(v[1], Fp[1], v[2] * Fp[2]));
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) Fp[a] = pe * F[a];
+            uF3 = A(3) * fmaa(v[0], Fp[0], fmaa(v[1], Fp[1], v[2] * Fp[2]));
+        }
     }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    // one-relaxation-time update of population i; its equilibrium into feq
+    auto post = [&](int i, A& feq) -> A {
         A cu = A(0);
         if (VSet<Q>::cx(i)) cu += VSet<Q>::cx(i) > 0 ? v[0] : -v[0];
         if (VSet<Q>::cy(i)) cu += VSet<Q>::cy(i) > 0 ? v[1] : -v[1];
         if (VSet<Q>::cz(i)) cu += VSet<Q>::cz(i) > 0 ? v[2] : -v[2];
         const A wi = A(VSet<Q>::w(i));
-        A feq;
         if (PR::shifted) {
             // h^eq = f^eq - w rho_ref = w [delta + rho (3cu + 4.5cu^2 - 1.5vv)]
             const A poly = fmaa(A(4.5) * cu, cu, fmaa(A(3), cu, A(-1.5) * vv));
@@ -330,19 +359,61 @@ __device__ __forceinline__ void relax_store(const typename PR::T (&fs)[Q], int s
         }
         const A fv = A(fs[i]);
         A fo = fmaa(om, feq - fv, fv);
-        if (GUO) {
+        if constexpr (PR::guo) {
             A cF = A(0);
             if (VSet<Q>::cx(i)) cF += VSet<Q>::cx(i) > 0 ? Fp[0] : -Fp[0];
             if (VSet<Q>::cy(i)) cF += VSet<Q>::cy(i) > 0 ? Fp[1] : -Fp[1];
             if (VSet<Q>::cz(i)) cF += VSet<Q>::cz(i) > 0 ? Fp[2] : -Fp[2];
             // (c_i - u).F / c_S^2 + (c_i.u)(c_i.F) / c_S^4 with c_S^2 = 1/3
-            const A t = fmaa(cF, fmaa(A(9), cu, A(3)), -uF3);
+            const A t = fmaa(cF, fmaa(c9, cu, c3), -uF3);
             fo = fmaa(wi, t, fo);
         }
+        return fo;
+    };
+    auto store = [&](int i, A fo) {
         buf_store_nt<T>(T(fo), make_rsrc(dst + (size_t)(s * Q + i) * pbytes, pbytes), voff, soff);
+    };
+    if constexpr (!PR::trt) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            A feq;
+            store(i, post(i, feq));
+        }
+    } else {
+        const A hd = A(0.5) * (om - omm);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int ib = opposite<Q>(i);
+            if (ib < i) continue;
+            A ei;
+            const A oi = post(i, ei);
+            if (ib == i) {
+                store(i, oi);
+                continue;
+            }
+            A eb;
+            const A ob = post(ib, eb);
+            const A B = (A(fs[i]) - A(fs[ib])) - (ei - eb);
+            store(i, fmaa(hd, B, oi));
+            store(ib, fmaa(-hd, B, ob));
+        }
     }
 }
 
+// Collision of one site and store of its 2Q post-collision populations.
+//   f      : the site's pulled populations f_is(x, t) (shifted h_is in FP32 mode)
+//   g[s]   : sum_i w_i rho_s(x + c_i) c_i, the gather of species s
+//   body   : external acceleration along x (0 without forcing)
+// The force on species s is F_s = rho_s a_s with a_s = -G g[s'] + body x.
+// tau-_s below is the odd-part relaxation time (tau_s for one relaxation time).
+// Velocity shift (the paper's scheme): the equilibrium of s is taken at
+// v_s = u' + tau-_s a_s, u' = sum_s j_s/tau-_s / sum_s rho_s/tau-_s.
+// Guo forcing (PR::guo): both species' equilibria at the common
+// u = sum_s (j_s + F_s/2)/tau-_s / sum_s rho_s/tau-_s, plus the source
+// S_is = (1 - 1/(2 tau_s)) w_i [3 (c_i - u).F_s + 9 (c_i.u)(c_i.F_s)].
+// Stores f*_is at byte offset soff + voff of the (s, i) arrays of dst.  Every
+// launch form (fused, two-pass, batched, persistent) calls this function, so
+// the per-site arithmetic is identical across them.
 template <int Q, class PR>
 __device__ __forceinline__ void collide_store(const typename PR::T (&f)[2][Q],
                                               const typename PR::A (&g)[2][3],
@@ -352,7 +423,9 @@ __device__ __forceinline__ void collide_store(const typename PR::T (&f)[2][Q],
     using A = typename PR::A;
     pbytes = opaque_sgpr(pbytes);
     const A om[2] = {A(p.omega[0]), A(p.omega[1])};
-    const A tau[2] = {A(p.tau[0]), A(p.tau[1])};
+    // the odd relaxation times weight the momenta and scale the force shift
+    const A omm[2] = {A(p.omega_m[0]), A(p.omega_m[1])};
+    const A taum[2] = {A(p.tau_m[0]), A(p.tau_m[1])};
     const A G = A(p.G);
     A rho[2], rfull[2], j[2][3];
 #pragma unroll
@@ -381,7 +454,7 @@ __device__ __forceinline__ void collide_store(const typename PR::T (&f)[2][Q],
         for (int a = 0; a < 3; ++a) acc[s][a] = -G * g[1 - s][a];
         acc[s][0] += bx;
     }
-    const A den = fmaa(rfull[0], om[0], rfull[1] * om[1]);
+    const A den = fmaa(rfull[0], omm[0], rfull[1] * omm[1]);
     if constexpr (PR::guo) {
         // Guo: common velocity of the momenta corrected by half the force
         A u[3];
@@ -389,28 +462,28 @@ __device__ __forceinline__ void collide_store(const typename PR::T (&f)[2][Q],
         for (int a = 0; a < 3; ++a) {
             const A mA = fmaa(A(0.5) * rfull[0], acc[0][a], j[0][a]);
             const A mB = fmaa(A(0.5) * rfull[1], acc[1][a], j[1][a]);
-            u[a] = fmaa(mA, om[0], mB * om[1]) / den;
+            u[a] = fmaa(mA, omm[0], mB * omm[1]) / den;
         }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             A F[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) F[a] = rfull[s] * acc[s][a];
-            relax_store<Q, PR, true>(f[s], s, u, F, rho[s], rfull[s], om[s], dst, pbytes, voff,
-                                     soff);
+            relax_store<Q, PR>(f[s], s, u, F, rho[s], rfull[s], om[s], omm[s], dst, pbytes, voff,
+                               soff);
         }
     } else {
         // velocity shift: common velocity u', then v_s = u' + tau_s a_s
         A u[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) u[a] = fmaa(j[0][a], om[0], j[1][a] * om[1]) / den;
+        for (int a = 0; a < 3; ++a) u[a] = fmaa(j[0][a], omm[0], j[1][a] * omm[1]) / den;
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             A v[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) v[a] = fmaa(tau[s], acc[s][a], u[a]);
-            relax_store<Q, PR, false>(f[s], s, v, v, rho[s], rfull[s], om[s], dst, pbytes, voff,
-                                      soff);
+            for (int a = 0; a < 3; ++a) v[a] = fmaa(taum[s], acc[s][a], u[a]);
+            relax_store<Q, PR>(f[s], s, v, v, rho[s], rfull[s], om[s], omm[s], dst, pbytes, voff,
+                               soff);
         }
     }
 }
@@ -950,5 +1023,27 @@ struct TileStepRepull {
         }
     }
 };
+
+// ---------------------------------------------------------------------------
+// Site helpers for the simple (one thread per site) kernels.
+// ---------------------------------------------------------------------------
+struct SiteGeom {
+    int x, y, z;
+};
+
+__device__ __forceinline__ SiteGeom site_xyz(uint32_t site, int nx, int ny) {
+    SiteGeom g;
+    g.x = (int)(site % (uint32_t)nx);
+    const uint32_t r = site / (uint32_t)nx;
+    g.y = (int)(r % (uint32_t)ny);
+    g.z = (int)(r / (uint32_t)ny);
+    return g;
+}
+
+__device__ __forceinline__ uint32_t site_at(const SiteGeom& g, int dx, int dy, int dz, int nx,
+                                            int ny, int nz) {
+    const int x = wrapi(g.x + dx, nx), y = wrapi(g.y + dy, ny), z = wrapi(g.z + dz, nz);
+    return ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)nx + (uint32_t)x;
+}
 
 }  // namespace sc

@@ -36,15 +36,41 @@ int tile_count(int Q);
 bool tile_get(int Q, int k, int* tx, int* ty);
 bool tile_supported(int Q, int tx, int ty);
 
-// Step-kernel policy index: storage precision (0 FP64, 1 FP32 shifted) plus
-// 2 for the Guo forcing (PF64, PF32S, PF64G, PF32SG).
-inline int step_policy(int precision, int forcing) { return precision + 2 * (forcing != 0); }
+// Step-kernel policy index: storage precision (0 FP64, 1 FP32 shifted), + 2
+// for the Guo forcing, + 4 for two relaxation times, in the order
+// PF64, PF32S, PF64G, PF32SG, PF64T, PF32ST, PF64GT, PF32SGT.
+constexpr int kPolicies = 8;
+inline int step_policy(int precision, int forcing, bool trt) {
+    return precision + 2 * (forcing != 0) + 4 * (trt ? 1 : 0);
+}
 
-// single-lattice launches (pol: step_policy)
-hipError_t launch_fused(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s);
-hipError_t launch_repull(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s);
-hipError_t launch_pipe(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s);
-hipError_t launch_twopass(int Q, int pol, const StepParams& p, void* psi, hipStream_t s);
+// Batched launches: per-lattice descriptor, work item and the sync words of
+// the persistent form.
+struct BatchDesc {
+    StepParams sp[2];  // parity 0 / 1 (source and destination swapped)
+    int Q;
+    int base_parity;   // buffer holding the state at epoch start
+    int steps;         // steps of this epoch
+    int pad;
+};
+
+struct WorkItem {
+    int member, tile_x, tile_y, chunk;
+};
+
+// sync words: [0] barrier count, [1] barrier generation, [2] timeout flag,
+// [3..3+K) per-step tile claim counters
+constexpr int SYNC_COUNT = 0, SYNC_GEN = 1, SYNC_TIMEOUT = 2, SYNC_CTR = 3;
+constexpr unsigned kSpinLimit = 1u << 26;  // ~seconds of s_sleep polling per barrier
+
+using BatchStepFn = void (*)(const BatchDesc*, const WorkItem*, int, int);
+using BatchPersFn = void (*)(const BatchDesc*, const WorkItem*, int, int, unsigned*);
+
+// single-lattice step of policy pol (variant 0 fused, 1 two-pass, 2 pipelined,
+// 3 re-pull); batch kernels of policy pol for a block shape
+hipError_t launch_step(int variant, int Q, int pol, int tx, int ty, const StepParams& p,
+                       void* psi, hipStream_t s);
+bool batch_kernels(int pol, int nt, int tx19, int ty19, BatchStepFn* sf, BatchPersFn* pf);
 hipError_t launch_init(int Q, int prec, void* f, const double* rho, const double* u, int nx,
                        int ny, int nz, const double* rho_ref, hipStream_t s);
 hipError_t launch_get_plane(int Q, int prec, const void* f, double* out, int s_, int i, int nx,

@@ -5,7 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
-#include "sc_internal.h"
+#include "sc_steps.h"
 
 namespace sc {
 
@@ -41,296 +41,35 @@ bool tile_supported(int Q, int tx, int ty) {
 }
 
 // ---------------------------------------------------------------------------
-// Fused step: one block per (tile, march chunk).
+// Policy dispatch (the kernels are instantiated in sc_step_<policy>.hip).
 // ---------------------------------------------------------------------------
-// Minimum waves per SIMD the register allocator must allow for the fused
-// step: two planes of populations stay in registers without scratch at
-// 2 waves (D3Q19 FP64, 218 VGPRs), 3 (D2Q9 FP64, D3Q19 FP32) and 4 (D2Q9 FP32).
-template <int Q, class PR>
-struct FusedWaves {
-    static constexpr int value = PR::shifted ? (Q == 19 ? 3 : 4) : (Q == 19 ? 2 : 3);
-};
-
-template <int Q, class PR, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY)
-    __attribute__((amdgpu_waves_per_eu(FusedWaves<Q, PR>::value))) k_step_fused(StepParams p) {
-    using TS = TileStep<Q, PR, TX, TY>;
-    __shared__ typename PR::A lds[TS::LDS_ELEMS];
-    const int w = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int tiles = p.ntx * p.nty;
-    const int chunk = w / tiles;
-    const int t = w - chunk * tiles;
-    TS::run(p, t % p.ntx, t / p.ntx, chunk, lds);
-}
-
-template <int Q, class PR, int TX, int TY>
-static hipError_t launch_fused_t(const StepParams& p, hipStream_t s) {
-    const unsigned nblk = (unsigned)p.ntx * p.nty * p.nchunks;
-    hipLaunchKernelGGL((k_step_fused<Q, PR, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, p);
-    return hipGetLastError();
-}
-
-template <class PR>
-static hipError_t launch_fused_p(int Q, int tx, int ty, const StepParams& p, hipStream_t s) {
-    if (Q == 9) {
-        switch (tx) {
-            case 64: return launch_fused_t<9, PR, 64, 1>(p, s);
-            case 128: return launch_fused_t<9, PR, 128, 1>(p, s);
-            case 256: return launch_fused_t<9, PR, 256, 1>(p, s);
-            case 512: return launch_fused_t<9, PR, 512, 1>(p, s);
-        }
-    } else {
-        const int key = tx * 1000 + ty;
-        switch (key) {
-            case 32004: return launch_fused_t<19, PR, 32, 4>(p, s);
-            case 64004: return launch_fused_t<19, PR, 64, 4>(p, s);
-            case 32008: return launch_fused_t<19, PR, 32, 8>(p, s);
-            case 64008: return launch_fused_t<19, PR, 64, 8>(p, s);
-            case 16016: return launch_fused_t<19, PR, 16, 16>(p, s);
-            case 32016: return launch_fused_t<19, PR, 32, 16>(p, s);
-        }
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_fused(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s) {
+hipError_t launch_step(int variant, int Q, int pol, int tx, int ty, const StepParams& p,
+                       void* psi, hipStream_t s) {
     switch (pol) {
-        case 0: return launch_fused_p<PF64>(Q, tx, ty, p, s);
-        case 1: return launch_fused_p<PF32S>(Q, tx, ty, p, s);
-        case 2: return launch_fused_p<PF64G>(Q, tx, ty, p, s);
-        case 3: return launch_fused_p<PF32SG>(Q, tx, ty, p, s);
+        case 0: return step_launch<PF64>(variant, Q, tx, ty, p, psi, s);
+        case 1: return step_launch<PF32S>(variant, Q, tx, ty, p, psi, s);
+        case 2: return step_launch<PF64G>(variant, Q, tx, ty, p, psi, s);
+        case 3: return step_launch<PF32SG>(variant, Q, tx, ty, p, psi, s);
+        case 4: return step_launch<PF64T>(variant, Q, tx, ty, p, psi, s);
+        case 5: return step_launch<PF32ST>(variant, Q, tx, ty, p, psi, s);
+        case 6: return step_launch<PF64GT>(variant, Q, tx, ty, p, psi, s);
+        case 7: return step_launch<PF32SGT>(variant, Q, tx, ty, p, psi, s);
     }
     return hipErrorInvalidValue;
 }
 
-// Pipelined march: three register planes; one wave per SIMD for D3Q19 FP64,
-// two for D3Q19 FP32 and D2Q9 FP64, three for D2Q9 FP32.
-template <int Q, class PR>
-struct PipeWaves {
-    static constexpr int value = PR::shifted ? (Q == 19 ? 2 : 3) : (Q == 19 ? 1 : 2);
-};
-
-template <int Q, class PR, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY)
-    __attribute__((amdgpu_waves_per_eu(PipeWaves<Q, PR>::value))) k_step_pipe(StepParams p) {
-    using TS = TileStepPipe<Q, PR, TX, TY>;
-    __shared__ typename PR::A lds[TS::LDS_ELEMS];
-    const int w = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int tiles = p.ntx * p.nty;
-    const int chunk = w / tiles;
-    const int t = w - chunk * tiles;
-    TS::run(p, t % p.ntx, t / p.ntx, chunk, lds);
-}
-
-template <int Q, class PR, int TX, int TY>
-static hipError_t launch_pipe_t(const StepParams& p, hipStream_t s) {
-    const unsigned nblk = (unsigned)p.ntx * p.nty * p.nchunks;
-    hipLaunchKernelGGL((k_step_pipe<Q, PR, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, p);
-    return hipGetLastError();
-}
-
-template <class PR>
-static hipError_t launch_pipe_p(int Q, int tx, int ty, const StepParams& p, hipStream_t s) {
-    if (Q == 9) {
-        switch (tx) {
-            case 64: return launch_pipe_t<9, PR, 64, 1>(p, s);
-            case 128: return launch_pipe_t<9, PR, 128, 1>(p, s);
-            case 256: return launch_pipe_t<9, PR, 256, 1>(p, s);
-            case 512: return launch_pipe_t<9, PR, 512, 1>(p, s);
-        }
-    } else {
-        const int key = tx * 1000 + ty;
-        switch (key) {
-            case 32004: return launch_pipe_t<19, PR, 32, 4>(p, s);
-            case 64004: return launch_pipe_t<19, PR, 64, 4>(p, s);
-            case 32008: return launch_pipe_t<19, PR, 32, 8>(p, s);
-            case 64008: return launch_pipe_t<19, PR, 64, 8>(p, s);
-            case 16016: return launch_pipe_t<19, PR, 16, 16>(p, s);
-            case 32016: return launch_pipe_t<19, PR, 32, 16>(p, s);
-        }
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_pipe(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s) {
+bool batch_kernels(int pol, int nt, int tx19, int ty19, BatchStepFn* sf, BatchPersFn* pf) {
     switch (pol) {
-        case 0: return launch_pipe_p<PF64>(Q, tx, ty, p, s);
-        case 1: return launch_pipe_p<PF32S>(Q, tx, ty, p, s);
-        case 2: return launch_pipe_p<PF64G>(Q, tx, ty, p, s);
-        case 3: return launch_pipe_p<PF32SG>(Q, tx, ty, p, s);
+        case 0: return batch_fns<PF64>(nt, tx19, ty19, sf, pf);
+        case 1: return batch_fns<PF32S>(nt, tx19, ty19, sf, pf);
+        case 2: return batch_fns<PF64G>(nt, tx19, ty19, sf, pf);
+        case 3: return batch_fns<PF32SG>(nt, tx19, ty19, sf, pf);
+        case 4: return batch_fns<PF64T>(nt, tx19, ty19, sf, pf);
+        case 5: return batch_fns<PF32ST>(nt, tx19, ty19, sf, pf);
+        case 6: return batch_fns<PF64GT>(nt, tx19, ty19, sf, pf);
+        case 7: return batch_fns<PF32SGT>(nt, tx19, ty19, sf, pf);
     }
-    return hipErrorInvalidValue;
-}
-
-
-// Re-pull march: one register plane; three waves per SIMD for FP64, four for FP32.
-template <int Q, class PR>
-struct RepullWaves {
-    // the Guo collision holds the force and its dot products: one wave less
-    static constexpr int value = (PR::shifted ? 4 : 3) - (PR::guo ? 1 : 0);
-};
-
-template <int Q, class PR, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY)
-    __attribute__((amdgpu_waves_per_eu(RepullWaves<Q, PR>::value))) k_step_repull(StepParams p) {
-    using TS = TileStepRepull<Q, PR, TX, TY>;
-    __shared__ typename PR::A lds[TS::LDS_ELEMS];
-    const int w = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int tiles = p.ntx * p.nty;
-    const int chunk = w / tiles;
-    const int t = w - chunk * tiles;
-    TS::run(p, t % p.ntx, t / p.ntx, chunk, lds);
-}
-
-template <int Q, class PR, int TX, int TY>
-static hipError_t launch_repull_t(const StepParams& p, hipStream_t s) {
-    const unsigned nblk = (unsigned)p.ntx * p.nty * p.nchunks;
-    hipLaunchKernelGGL((k_step_repull<Q, PR, TX, TY>), dim3(nblk), dim3(TX * TY), 0, s, p);
-    return hipGetLastError();
-}
-
-template <class PR>
-static hipError_t launch_repull_p(int Q, int tx, int ty, const StepParams& p, hipStream_t s) {
-    if (Q == 9) {
-        switch (tx) {
-            case 64: return launch_repull_t<9, PR, 64, 1>(p, s);
-            case 128: return launch_repull_t<9, PR, 128, 1>(p, s);
-            case 256: return launch_repull_t<9, PR, 256, 1>(p, s);
-            case 512: return launch_repull_t<9, PR, 512, 1>(p, s);
-        }
-    } else {
-        const int key = tx * 1000 + ty;
-        switch (key) {
-            case 32004: return launch_repull_t<19, PR, 32, 4>(p, s);
-            case 64004: return launch_repull_t<19, PR, 64, 4>(p, s);
-            case 32008: return launch_repull_t<19, PR, 32, 8>(p, s);
-            case 64008: return launch_repull_t<19, PR, 64, 8>(p, s);
-            case 16016: return launch_repull_t<19, PR, 16, 16>(p, s);
-            case 32016: return launch_repull_t<19, PR, 32, 16>(p, s);
-        }
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_repull(int Q, int pol, int tx, int ty, const StepParams& p, hipStream_t s) {
-    switch (pol) {
-        case 0: return launch_repull_p<PF64>(Q, tx, ty, p, s);
-        case 1: return launch_repull_p<PF32S>(Q, tx, ty, p, s);
-        case 2: return launch_repull_p<PF64G>(Q, tx, ty, p, s);
-        case 3: return launch_repull_p<PF32SG>(Q, tx, ty, p, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-// ---------------------------------------------------------------------------
-// Site helpers for the simple (one thread per site) kernels.
-// ---------------------------------------------------------------------------
-struct SiteGeom {
-    int x, y, z;
-};
-
-__device__ __forceinline__ SiteGeom site_xyz(uint32_t site, int nx, int ny) {
-    SiteGeom g;
-    g.x = (int)(site % (uint32_t)nx);
-    const uint32_t r = site / (uint32_t)nx;
-    g.y = (int)(r % (uint32_t)ny);
-    g.z = (int)(r / (uint32_t)ny);
-    return g;
-}
-
-__device__ __forceinline__ uint32_t site_at(const SiteGeom& g, int dx, int dy, int dz, int nx,
-                                            int ny, int nz) {
-    const int x = wrapi(g.x + dx, nx), y = wrapi(g.y + dy, ny), z = wrapi(g.z + dz, nz);
-    return ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)nx + (uint32_t)x;
-}
-
-// ---------------------------------------------------------------------------
-// Two-pass step: densities to an HBM psi array, then collide with a global
-// gather.  Moves (6Q + 4) values per site instead of 4Q; kept as the plain
-// form the fused kernel is measured against.
-// ---------------------------------------------------------------------------
-template <int Q, class PR>
-__global__ void __launch_bounds__(256) k_density(StepParams p, typename PR::A* psi, int nx, int ny,
-                                                 int nz) {
-    using T = typename PR::T;
-    using A = typename PR::A;
-    const uint32_t site = blockIdx.x * 256u + threadIdx.x;
-    if (site >= p.N) return;
-    const T* f = static_cast<const T*>(p.src);
-    const SiteGeom g = site_xyz(site, nx, ny);
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        A r = A(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            r += A(f[(size_t)(s * Q + i) * p.N +
-                     site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)]);
-        psi[(size_t)s * p.N + site] = r;
-    }
-}
-
-template <int Q, class PR>
-__global__ void __launch_bounds__(256) k_collide2(StepParams p, const typename PR::A* psi, int nx,
-                                                  int ny, int nz) {
-    using T = typename PR::T;
-    using A = typename PR::A;
-    const uint32_t site = blockIdx.x * 256u + threadIdx.x;
-    if (site >= p.N) return;
-    const T* f = static_cast<const T*>(p.src);
-    const SiteGeom g = site_xyz(site, nx, ny);
-    T v[2][Q];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            v[s][i] = f[(size_t)(s * Q + i) * p.N +
-                        site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)];
-    A gs[2][3];
-    gather<Q>([&](int s, int i) {
-        return psi[(size_t)s * p.N +
-                   site_at(g, VSet<Q>::cx(i), VSet<Q>::cy(i), VSet<Q>::cz(i), nx, ny, nz)];
-    }, gs);
-    const double body = p.body_A != 0.0 ? kolmogorov(p, g.y) : 0.0;
-    collide_store<Q, PR>(v, gs, p, body, static_cast<char*>(p.dst), p.N * (uint32_t)sizeof(T),
-                         site * (uint32_t)sizeof(T), 0u);
-}
-
-template <int Q, class PR>
-static hipError_t launch_twopass_t(const StepParams& p, void* psi, hipStream_t s) {
-    using A = typename PR::A;
-    const unsigned nblk = (p.N + 255u) / 256u;
-    int nx, ny, nz;
-    if (Q == 19) {
-        nx = p.NX;
-        ny = p.NY;
-        nz = p.NM;
-    } else {
-        nx = p.NX;
-        ny = p.NM;
-        nz = 1;
-    }
-    hipLaunchKernelGGL((k_density<Q, PR>), dim3(nblk), dim3(256), 0, s, p, static_cast<A*>(psi),
-                       nx, ny, nz);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_collide2<Q, PR>), dim3(nblk), dim3(256), 0, s, p,
-                       static_cast<const A*>(psi), nx, ny, nz);
-    return hipGetLastError();
-}
-
-template <int Q>
-static hipError_t launch_twopass_q(int pol, const StepParams& p, void* psi, hipStream_t s) {
-    switch (pol) {
-        case 0: return launch_twopass_t<Q, PF64>(p, psi, s);
-        case 1: return launch_twopass_t<Q, PF32S>(p, psi, s);
-        case 2: return launch_twopass_t<Q, PF64G>(p, psi, s);
-        case 3: return launch_twopass_t<Q, PF32SG>(p, psi, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_twopass(int Q, int pol, const StepParams& p, void* psi, hipStream_t s) {
-    return Q == 9 ? launch_twopass_q<9>(pol, p, psi, s) : launch_twopass_q<19>(pol, p, psi, s);
+    return false;
 }
 
 // ---------------------------------------------------------------------------

@@ -45,6 +45,18 @@ struct lbm_sc {
     lbm_batch* batch = nullptr;  // batch this handle belongs to, if any
 };
 
+// Odd-part relaxation time of species s (tau_minus <= 0 means tau_s: BGK).
+inline double sc_tau_minus(const lbm_sc_params& p, int s) {
+    const double tm = s == 0 ? p.tau_minus_A : p.tau_minus_B;
+    return tm > 0.0 ? tm : (s == 0 ? p.tau_A : p.tau_B);
+}
+
+// Kernel policy of a lattice (sc::step_policy index).
+inline int sc_policy(const lbm_sc_params& p) {
+    const bool trt = sc_tau_minus(p, 0) != p.tau_A || sc_tau_minus(p, 1) != p.tau_B;
+    return sc::step_policy(p.precision, p.forcing, trt);
+}
+
 Layout sc_layout(const lbm_sc_params* p);
 void sc_default_kernel(int Q, int nx, int ny, int nz, int* tx, int* ty, int* mb);
 sc::StepParams sc_step_params(const lbm_sc* h, int parity);

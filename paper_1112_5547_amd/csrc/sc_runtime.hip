@@ -41,6 +41,8 @@ int validate(const lbm_sc_params* p) {
     if (p->precision != LBM_FP64 && p->precision != LBM_FP32_SHIFTED) return LBM_EINVAL;
     if (!isfinite(p->body_A) || !isfinite(p->rho_ref_A) || !isfinite(p->rho_ref_B)) return LBM_EINVAL;
     if (p->forcing != LBM_FORCING_SHIFT && p->forcing != LBM_FORCING_GUO) return LBM_EINVAL;
+    for (double tm : {p->tau_minus_A, p->tau_minus_B})
+        if (!isfinite(tm) || (tm > 0.0 && !(tm > 0.5))) return LBM_EINVAL;
     return LBM_OK;
 }
 
@@ -126,6 +128,10 @@ StepParams sc_step_params(const lbm_sc* h, int parity) {
     sp.tau[1] = p.tau_B;
     sp.omega[0] = 1.0 / p.tau_A;
     sp.omega[1] = 1.0 / p.tau_B;
+    for (int s = 0; s < 2; ++s) {
+        sp.tau_m[s] = sc_tau_minus(p, s);
+        sp.omega_m[s] = 1.0 / sp.tau_m[s];
+    }
     sp.G = p.G;
     sp.rho_ref[0] = h->rho_ref[0];
     sp.rho_ref[1] = h->rho_ref[1];
@@ -136,11 +142,7 @@ StepParams sc_step_params(const lbm_sc* h, int parity) {
 
 hipError_t sc_launch_step(lbm_sc* h, int parity, hipStream_t s) {
     const StepParams sp = sc_step_params(h, parity);
-    const int pol = step_policy(h->p.precision, h->p.forcing);
-    if (h->variant == 1) return launch_twopass(h->Q, pol, sp, h->psi, s);
-    if (h->variant == 2) return launch_pipe(h->Q, pol, h->tx, h->ty, sp, s);
-    if (h->variant == 3) return launch_repull(h->Q, pol, h->tx, h->ty, sp, s);
-    return launch_fused(h->Q, pol, h->tx, h->ty, sp, s);
+    return launch_step(h->variant, h->Q, sc_policy(h->p), h->tx, h->ty, sp, h->psi, s);
 }
 
 namespace {
@@ -246,6 +248,7 @@ int lbm_sc_params_default(lbm_sc_params* p, int lattice, int nx, int ny, int nz,
     p->rho_ref_B = 0.0;
     p->body_A = 0.0;
     p->forcing = LBM_FORCING_SHIFT;
+    p->tau_minus_A = p->tau_minus_B = 0.0;
     return validate(p);
 }
 

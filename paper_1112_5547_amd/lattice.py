@@ -26,13 +26,17 @@ class Lattice:
     precision: "fp64" or "fp32_shifted"; rho_ref: (A, B) reference densities of
     the shifted storage (default: the mean of the initial densities);
     body_A: Kolmogorov forcing amplitude (F_x = rho_s A sin(2 pi y / ny));
-    forcing: "shift" (the paper's velocity shift) or "guo" (Guo discrete forcing).
+    forcing: "shift" (the paper's velocity shift) or "guo" (Guo discrete forcing);
+    tau_minus: (tau-_A, tau-_B) relaxation times of the odd moments (two
+    relaxation times: viscosity from tau_s, interdiffusion from tau-_s); None
+    keeps one relaxation time (BGK).
     """
 
     def __init__(self, lattice: int, nx: int, ny: int, nz: int = 1, *, tau_A: float = 1.0,
                  tau_B: Optional[float] = None, G: float = 0.0, precision: str = "fp64",
                  rho_ref: Optional[Tuple[float, float]] = None, body_A: float = 0.0,
-                 forcing: str = "shift", device: Optional[int] = None, use_torch: bool = True):
+                 forcing: str = "shift", tau_minus: Optional[Tuple[float, float]] = None,
+                 device: Optional[int] = None, use_torch: bool = True):
         L = lib()
         p = Params()
         check(L.lbm_sc_params_default(ctypes.byref(p), lattice, nx, ny, nz, tau_A,
@@ -44,7 +48,10 @@ class Lattice:
         if forcing not in _FORCING:
             raise ValueError(f"forcing must be one of {sorted(_FORCING)}")
         p.forcing = _FORCING[forcing]
+        if tau_minus is not None:
+            p.tau_minus_A, p.tau_minus_B = float(tau_minus[0]), float(tau_minus[1])
         self.forcing = forcing
+        self.tau_minus = tau_minus
         self.params = p
         self.q = lattice
         self.shape = (nz, ny, nx)

@@ -13,11 +13,11 @@ def say(msg: str):
 
 
 def gpu_run(q, rho_A, rho_B, tau_A, tau_B, G, steps, *, precision="fp64", kernel=None,
-            body_A=0.0, u=None, forcing="shift"):
+            body_A=0.0, u=None, forcing="shift", tau_minus=None):
     from paper_1112_5547_amd import Lattice
     nz, ny, nx = rho_A.shape
     lat = Lattice(q, nx, ny, nz, tau_A=tau_A, tau_B=tau_B, G=G, precision=precision,
-                  body_A=body_A, forcing=forcing)
+                  body_A=body_A, forcing=forcing, tau_minus=tau_minus)
     if kernel is not None:
         lat.set_kernel(*kernel)
     lat.init(rho_A, rho_B, u)
@@ -26,9 +26,11 @@ def gpu_run(q, rho_A, rho_B, tau_A, tau_B, G, steps, *, precision="fp64", kernel
     return lat, f
 
 
-def oracle_run(q, rho_A, rho_B, tau_A, tau_B, G, steps, body_A=0.0, u=None, forcing="shift"):
+def oracle_run(q, rho_A, rho_B, tau_A, tau_B, G, steps, body_A=0.0, u=None, forcing="shift",
+               tau_minus=None):
     f0 = oracle.init(q, rho_A, rho_B, u)
-    return oracle.run(f0, tau_A, tau_B, G, steps, body_A=body_A, forcing=forcing)
+    return oracle.run(f0, tau_A, tau_B, G, steps, body_A=body_A, forcing=forcing,
+                      tau_minus=tau_minus)
 
 
 def maxabs(a, b):

@@ -68,6 +68,13 @@ def test_params_validation_and_sizes():
     assert L.lbm_sc_bytes_needed(ctypes.byref(f)) > 0
     f.forcing = 2
     assert L.lbm_sc_bytes_needed(ctypes.byref(f)) == 0
+    # odd-part relaxation times: 0 (BGK) or > 1/2
+    f.forcing = 0
+    assert f.tau_minus_A == 0.0 and f.tau_minus_B == 0.0
+    f.tau_minus_A, f.tau_minus_B = 0.7, 1.3
+    assert L.lbm_sc_bytes_needed(ctypes.byref(f)) > 0
+    f.tau_minus_B = 0.5
+    assert L.lbm_sc_bytes_needed(ctypes.byref(f)) == 0
     bad = [
         (9, 8, 8, 2, 1.0, 1.0, 1.0),     # D2Q9 with nz > 1
         (19, 0, 8, 8, 1.0, 1.0, 1.0),    # empty lattice

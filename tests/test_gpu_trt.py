@@ -1,0 +1,129 @@
+"""Two relaxation times on the GPU path (the odd moments relaxed with tau-,
+the MRT member that decouples viscosity and interdiffusion, Sec. 2.1's
+closing remark): FP64 parity with the oracle (<= 1e-12) for both forcing
+schemes, FP32 shifted within the FP32 bound, every kernel variant bitwise
+equal, a batch mixing BGK and two-relaxation-time members bitwise equal to
+solo runs, and the decoupling itself measured from GPU runs: a shear wave
+decays with nu = c_S^2 (tau+ - 1/2), an order-parameter wave with
+D = c_S^2 (tau- - 1/2)."""
+import numpy as np
+import pytest
+
+import sc_inputs
+from gpu_common import gpu_run, maxabs, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+
+TM = (1.3, 0.65)
+
+
+@pytest.mark.parametrize("forcing", ["shift", "guo"])
+@pytest.mark.parametrize("q,shape,steps", [(9, (1, 64, 64), 100), (19, (16, 20, 24), 60)])
+def test_trt_fp64_matches_oracle(q, shape, steps, forcing):
+    nz, ny, nx = shape
+    fl = sc_inputs.drop(nx, ny, nz, radius=min(nx, ny) / 4, seed=6)
+    say(f"trt fp64 q={q} {shape} {forcing}")
+    lat, f = gpu_run(q, fl.rho_A, fl.rho_B, 0.8, 1.1, 1.3, steps, body_A=1e-5, forcing=forcing,
+                     tau_minus=TM)
+    lat.close()
+    ref = oracle_run(q, fl.rho_A, fl.rho_B, 0.8, 1.1, 1.3, steps, body_A=1e-5, forcing=forcing,
+                     tau_minus=TM)
+    assert maxabs(f, ref) <= 1e-12
+
+
+def test_trt_fp32_shifted_within_fp32_bounds():
+    fl = sc_inputs.drop(64, 64, 1, radius=16, seed=1)
+    say("trt fp32_shifted 64^2")
+    lat, f = gpu_run(9, fl.rho_A, fl.rho_B, 1.0, 1.0, 1.3, 100, precision="fp32_shifted",
+                     tau_minus=(0.8, 0.8))
+    lat.close()
+    ref = oracle_run(9, fl.rho_A, fl.rho_B, 1.0, 1.0, 1.3, 100, tau_minus=(0.8, 0.8))
+    assert maxabs(f, ref) <= 2e-6
+
+
+@pytest.mark.parametrize("precision,forcing", [("fp64", "shift"), ("fp32_shifted", "guo")])
+def test_trt_variants_agree_bitwise(precision, forcing):
+    fl = sc_inputs.drop(40, 36, 30, radius=8, seed=3)
+    ref = None
+    for k in [(0, 64, 4, 8), (0, 32, 8, 3), (1, 64, 4, 4), (2, 64, 4, 8), (3, 32, 16, 6)]:
+        say(f"trt variants {precision} {forcing} kernel {k}")
+        lat, f = gpu_run(19, fl.rho_A, fl.rho_B, 0.9, 1.1, 1.4, 30, precision=precision,
+                         kernel=k, forcing=forcing, tau_minus=TM)
+        lat.close()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f, ref), k
+
+
+def test_batch_mixing_bgk_and_trt_equals_solo():
+    from paper_1112_5547_amd import Batch, Lattice
+    specs = [(9, 64, 64, 1, None, 40), (9, 64, 64, 1, (1.4, 0.7), 40),
+             (19, 20, 20, 20, (0.7, 0.7), 33)]
+
+    def make(spec, seed):
+        q, nx, ny, nz, tm, _ = spec
+        fl = sc_inputs.drop(nx, ny, nz, radius=min(nx, ny) / 4, seed=seed)
+        lat = Lattice(q, nx, ny, nz, tau_A=0.9, tau_B=1.0, G=1.4, precision="fp64", tau_minus=tm)
+        lat.init(fl.rho_A, fl.rho_B)
+        return lat
+
+    solo = []
+    for k, spec in enumerate(specs):
+        say(f"solo {spec}")
+        lat = make(spec, 50 + k)
+        lat.step(spec[5])
+        solo.append(lat.get_populations())
+        lat.close()
+    say("batch of BGK and two-relaxation-time members")
+    b = Batch()
+    lats = [make(spec, 50 + k) for k, spec in enumerate(specs)]
+    for lat, spec in zip(lats, specs):
+        assert b.add(lat, spec[5])
+    for _ in range(8):
+        b.run(16, "fused")
+        if len(b.poll()) == len(lats):
+            break
+    for lat, spec, ref in zip(lats, specs, solo):
+        b.remove(lat)
+        assert np.array_equal(lat.get_populations(), ref), spec
+        lat.close()
+    b.close()
+
+
+def _decay(kind, tp, tm):
+    L, CS2 = 128, 1.0 / 3.0
+    k = 2 * np.pi / L
+    if kind == "shear":
+        shape = (1, L, 1)
+        y = np.arange(L, dtype=float).reshape(1, L, 1)
+        u = np.zeros((3,) + shape)
+        u[0] = 1e-4 * np.sin(k * y)
+        rA = rB = np.full(shape, 0.5)
+        coord = y
+    else:
+        shape = (1, 1, L)
+        x = np.arange(L, dtype=float).reshape(1, 1, L)
+        phi = 1e-4 * np.sin(k * x)
+        rA, rB, u, coord = 0.5 + phi / 2, 0.5 - phi / 2, None, x
+    from paper_1112_5547_amd import Lattice
+    nz, ny, nx = shape
+    lat = Lattice(9, nx, ny, nz, tau_A=tp, G=0.0, precision="fp64", tau_minus=(tm, tm))
+    lat.init(rA, rB, u)
+    amps = []
+    for n in (400, 2400):
+        lat.step(n - (0 if not amps else 400))
+        a, b_, uu, _ = lat.moments()
+        field = uu[0] if kind == "shear" else a - b_
+        amps.append(2 * np.mean(field * np.sin(k * coord)))
+    lat.close()
+    return -np.log(amps[1] / amps[0]) / (2000 * k * k)
+
+
+@pytest.mark.parametrize("tp,tm", [(0.8, 1.4), (1.2, 0.6)])
+def test_viscosity_and_diffusion_decouple_on_the_gpu(tp, tm):
+    CS2 = 1.0 / 3.0
+    say(f"decoupling tau+ {tp} tau- {tm}")
+    nu, D = _decay("shear", tp, tm), _decay("phi", tp, tm)
+    assert abs(nu - CS2 * (tp - 0.5)) < 2e-3 * CS2 * (tp - 0.5)
+    assert abs(D - CS2 * (tm - 0.5)) < 2e-3 * CS2 * (tm - 0.5)
