@@ -202,8 +202,9 @@ def serve_leg(n_jobs: int, budget_gb: float, epoch: int):
     U{500..5000}, FP32 shifted.  The arrival rate offers 0.7 x the capacity of
     one-job-at-a-time service for this job mix (solo step times measured per
     lattice shape).  Served with continuous batching (shortest remaining work
-    first), and sequentially (one job at a time, one lattice per launch) on the
-    same arrivals."""
+    first with light aging; device-filling lattices and lone jobs step with
+    their tuned solo kernels), and sequentially (one job at a time, one
+    lattice per launch) on the same arrivals."""
     import sc_inputs
     from paper_1112_5547_amd import autotune
     from paper_1112_5547_amd.serve import (GpuBackend, Server, offered_rate, sequential_baseline,
@@ -218,7 +219,8 @@ def serve_leg(n_jobs: int, budget_gb: float, epoch: int):
               + sorted([j for j in jobs if j.lattice == 19], key=lambda j: j.sites)[:8])
     tiles = autotune.tune_batch(sample, precision="fp32_shifted", mode="fused", epoch=20)
     server = Server(hbm_budget=int(budget_gb * 1e9), epoch_steps=epoch, mode="fused",
-                    backend=GpuBackend("fp32_shifted"), tiles=tiles, policy="srpt")
+                    backend=GpuBackend("fp32_shifted"), tiles=tiles, policy="srpt",
+                    aging=0.25, nominal_rate=capacity * 1e6)
     rep = server.run(jobs)
     served = rep.summary()
     seq = sequential_baseline(jobs, backend=GpuBackend("fp32_shifted"))
@@ -229,7 +231,7 @@ def serve_leg(n_jobs: int, budget_gb: float, epoch: int):
                         f"{budget_gb:g} GB",
             "arrival_rate_per_s": round(rate, 4), "solo_capacity_mlups": round(capacity, 1),
             "batch_tiles": tiles, "mode": "fused", "policy": server.policy,
-            "sat_sites": server.sat_sites, "epoch_steps": epoch,
+            "sat_sites": server.sat_sites, "aging": server.aging, "epoch_steps": epoch,
             "nonfinite_jobs": [{"job": j.job_id, "tau": round(j.tau, 3), "G": round(j.G, 3)}
                                for j in jobs if j.job_id in served["nonfinite_jobs"]],
             "served": {k: r3(v) for k, v in served.items()},

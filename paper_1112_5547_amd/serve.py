@@ -12,11 +12,18 @@ counts) arrive over time.  The loop:
     - ``"srpt"`` (default): shortest remaining work first.  Resident jobs are
       ordered by remaining site updates and taken until their lattices hold
       ``sat_sites`` sites, the size at which one batch launch keeps the whole
-      device busy; the rest wait, resident, for a later epoch.  A small job
+      device busy; the rest wait, resident, for a later epoch.  A lattice of
+      ``sat_sites`` or more never joins a batch: the prefix stops before it,
+      and it runs alone once it is first in order.  A small job
       then never pays the step time of a large one, and a large job still runs
       at full rate once it is the shortest.  An epoch whose only member fills
       the device by itself (at least ``sat_sites`` sites) steps that lattice
-      alone with its own tuned kernel instead of the batch launch;
+      alone with its own tuned kernel instead of the batch launch, and so
+      does any lone member (``solo_alone``, the default).  With
+      ``aging`` > 0 the order key is the remaining work in seconds (at
+      ``nominal_rate`` site updates per second) minus ``aging`` times the time
+      the job has spent in the system, so that a large job cannot be passed
+      over indefinitely by a stream of smaller ones;
     - ``"all"``: every resident job advances every epoch (each job gets the
       same number of steps per epoch, whatever its size);
 * while an epoch runs on the device, prepares the next admissions on the host
@@ -148,11 +155,15 @@ class Server:
                  max_resident: int = 256, backend=None, clock=None,
                  keep_populations: bool = False, admit_hook: Optional[Callable] = None,
                  tiles: Optional[dict] = None, policy: str = "srpt",
-                 sat_sites: int = 4_000_000):
+                 sat_sites: int = 4_000_000, aging: float = 0.0,
+                 nominal_rate: float = 1e10, solo_alone: bool = True):
         if policy not in ("srpt", "all"):
             raise ValueError(f"unknown scheduling policy {policy!r}")
         self.policy = policy
         self.sat_sites = int(sat_sites)
+        self.aging = float(aging)
+        self.solo_alone = bool(solo_alone)
+        self.nominal_rate = float(nominal_rate)
         self.budget = int(hbm_budget)
         self.epoch_steps = int(epoch_steps)
         self.mode = mode
@@ -225,15 +236,30 @@ class Server:
             the device by itself, else None (the batch runs the epoch)."""
             if not srpt:
                 return None
-            order = sorted(resident, key=lambda j: (remaining(j) * resident[j][0].sites,
-                                                    resident[j][0].arrival, j))
+            now = clock.now()
+
+            def key(j):
+                job = resident[j][0]
+                work_s = remaining(j) * job.sites / self.nominal_rate
+                return (work_s - self.aging * (now - job.arrival), job.arrival, j)
+
+            order = sorted(resident, key=key)
             chosen, sites = [], 0
             for jid in order:
+                n = resident[jid][0].sites
+                if n >= self.sat_sites:
+                    # a lattice that fills the device never shares a batch (every
+                    # batch step would take its step time): it runs alone, once
+                    # it is the first in order
+                    if not chosen:
+                        chosen, sites = [jid], n
+                    break
                 if chosen and sites >= self.sat_sites:
                     break
                 chosen.append(jid)
-                sites += resident[jid][0].sites
-            solo = chosen[0] if len(chosen) == 1 and sites >= self.sat_sites else None
+                sites += n
+            lone = len(chosen) == 1 and (self.solo_alone or sites >= self.sat_sites)
+            solo = chosen[0] if lone else None
             keep = set() if solo is not None else set(chosen)
             for jid in sorted(active - keep):
                 batch.remove(resident[jid][1])

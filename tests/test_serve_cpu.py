@@ -261,10 +261,9 @@ def test_solo_capacity_is_work_over_summed_service_time():
 
 
 def test_srpt_steps_a_saturating_lone_job_by_itself():
-    """A job whose lattice alone reaches sat_sites runs solo launches when it
-    is the only member of an epoch; its result is still its solo result.  The
-    two small jobs and the big one form the saturating prefix for two epochs
-    (16 of the big job's steps in the batch); the other 14 run alone."""
+    """A job whose lattice alone reaches sat_sites never joins a batch: the
+    two small jobs run first (their remaining work is smaller), then the big
+    job's 30 steps all run as solo launches; every result is its solo result."""
     clock = SimClock()
     be = FakeBackend(clock)
     jobs = [_job(0, 20, 30, 0.0), _job(1, 6, 12, 0.0), _job(2, 7, 9, 0.0)]
@@ -272,7 +271,9 @@ def test_srpt_steps_a_saturating_lone_job_by_itself():
                  keep_populations=True).run(jobs)
     solo = [e for e in be.log if e[0] == "solo"]
     assert solo and all(e[1] == 0 for e in solo)
-    assert sum(e[2] for e in solo) == 30 - 16
+    assert sum(e[2] for e in solo) == 30
+    members = [e[1] for e in be.log if e[0] == "members"]
+    assert all(0 not in m for m in members)
     by_id = {r.job_id: r for r in rep.results}
     assert by_id[1].completed < by_id[0].completed and by_id[2].completed < by_id[0].completed
     for job in jobs:
@@ -280,3 +281,18 @@ def test_srpt_steps_a_saturating_lone_job_by_itself():
         ref = oracle.run(oracle.init(job.lattice, fl.rho_A, fl.rho_B), job.tau, job.tau, job.G,
                          job.steps)
         assert np.array_equal(by_id[job.job_id].populations, ref)
+
+
+def test_aging_lets_a_waiting_large_job_ahead_of_new_small_ones():
+    """A large job keeps losing to a stream of small ones under pure SRPT; with
+    aging its key drops with its waiting time and it completes earlier."""
+    done = {}
+    for aging in (0.0, 4.0):
+        clock = SimClock()
+        be = FakeBackend(clock, capacity=1e4)
+        # one 5.4 s job at t = 0, then 0.11 s jobs every 0.15 s
+        jobs = [_job(0, 30, 60, 0.0)] + [_job(k, 6, 30, 0.15 * k) for k in range(1, 40)]
+        rep = Server(hbm_budget=0, epoch_steps=10, backend=be, clock=clock, sat_sites=30,
+                     aging=aging, nominal_rate=1e4).run(jobs)
+        done[aging] = {r.job_id: r.completed for r in rep.results}
+    assert done[4.0][0] < done[0.0][0] - 1.0
