@@ -47,7 +47,7 @@ struct Member {
     long long remaining;
 };
 
-// One policy group's (precision, forcing) device tables and cached graph.
+// One kernel policy group's (precision, forcing, relaxation) device tables and cached graph.
 struct Group {
     BatchDesc* d_desc = nullptr;
     size_t desc_cap = 0;
@@ -147,10 +147,10 @@ int member_mb(const lbm_batch* b, const lbm_sc* h) {
     return o > 0 ? o : h->mb;
 }
 
-// Enqueues one epoch of the members of one policy group (precision and forcing).
-int run_group(lbm_batch* b, int prec, const std::vector<int>& idx, const std::vector<int>& ksteps,
+// Enqueues one epoch of the members of one kernel policy group.
+int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vector<int>& ksteps,
               int K, int mode) {
-    Group& g = b->grp[prec];
+    Group& g = b->grp[pol];
     // descriptors and the work list (largest-cost lattices first)
     struct Item {
         WorkItem w;
@@ -199,7 +199,7 @@ int run_group(lbm_batch* b, int prec, const std::vector<int>& idx, const std::ve
 
     BatchStepFn sf = nullptr;
     BatchPersFn pf = nullptr;
-    const bool ok = batch_kernels(prec, b->nt, b->tx19, b->ty19, &sf, &pf);
+    const bool ok = batch_kernels(pol, b->nt, b->tx19, b->ty19, &sf, &pf);
     if (!ok) return LBM_EINVAL;
 
     int grid = nwork;
@@ -326,36 +326,36 @@ int lbm_batch_run(lbm_batch* b, int epoch_steps, int mode) {
         Member& m = b->members[i];
         if (m.remaining <= 0 || m.h->err) continue;
         const int k = (int)std::min<long long>(m.remaining, epoch_steps);
-        const int prec = sc_policy(m.h->p);
-        idx[prec].push_back((int)i);
-        ks[prec].push_back(k);
+        const int pol = sc_policy(m.h->p);
+        idx[pol].push_back((int)i);
+        ks[pol].push_back(k);
     }
     if (mode == LBM_BATCH_PER_LATTICE) {
-        for (int prec = 0; prec < kPolicies; ++prec)
-            for (size_t m = 0; m < idx[prec].size(); ++m) {
-                lbm_sc* h = b->members[idx[prec][m]].h;
+        for (int pol = 0; pol < kPolicies; ++pol)
+            for (size_t m = 0; m < idx[pol].size(); ++m) {
+                lbm_sc* h = b->members[idx[pol][m]].h;
                 lbm_batch* keep = h->batch;
-                const int rc = sc_enqueue_steps(h, ks[prec][m], b->stream);
+                const int rc = sc_enqueue_steps(h, ks[pol][m], b->stream);
                 h->batch = keep;
                 if (rc) {
                     b->err = rc;
                     return rc;
                 }
                 // sc_enqueue_steps already advanced parity and step count
-                b->members[idx[prec][m]].remaining -= ks[prec][m];
+                b->members[idx[pol][m]].remaining -= ks[pol][m];
             }
         return LBM_OK;
     }
-    for (int prec = 0; prec < kPolicies; ++prec) {
-        if (idx[prec].empty()) continue;
-        const int K = *std::max_element(ks[prec].begin(), ks[prec].end());
-        const int rc = run_group(b, prec, idx[prec], ks[prec], K, mode);
+    for (int pol = 0; pol < kPolicies; ++pol) {
+        if (idx[pol].empty()) continue;
+        const int K = *std::max_element(ks[pol].begin(), ks[pol].end());
+        const int rc = run_group(b, pol, idx[pol], ks[pol], K, mode);
         if (rc) return rc;
-        for (size_t m = 0; m < idx[prec].size(); ++m) {
-            Member& mm = b->members[idx[prec][m]];
-            mm.h->cur ^= (ks[prec][m] & 1);
-            mm.h->steps += ks[prec][m];
-            mm.remaining -= ks[prec][m];
+        for (size_t m = 0; m < idx[pol].size(); ++m) {
+            Member& mm = b->members[idx[pol][m]];
+            mm.h->cur ^= (ks[pol][m] & 1);
+            mm.h->steps += ks[pol][m];
+            mm.remaining -= ks[pol][m];
         }
     }
     return LBM_OK;
@@ -367,8 +367,8 @@ int lbm_batch_poll(lbm_batch* b, lbm_sc** done, int max_done, int* n_done) {
     if (b->err) return b->err;
     (void)hipSetDevice(b->device);
     BCALL(b, hipStreamSynchronize(b->stream));
-    for (int prec = 0; prec < kPolicies; ++prec) {
-        Group& g = b->grp[prec];
+    for (int pol = 0; pol < kPolicies; ++pol) {
+        Group& g = b->grp[pol];
         if (g.d_sync && g.g_mode == LBM_BATCH_PERSISTENT) {
             unsigned flag = 0;
             BCALL(b, hipMemcpy(&flag, g.d_sync + SYNC_TIMEOUT, sizeof(unsigned),
