@@ -146,6 +146,39 @@ def paper_drop_kolmogorov(precision: str = "fp64", *, L: int = 100, steps_static
             "ke_single_phase": L * L * (A / (nu * k * k)) ** 2 / 2.0}
 
 
+def laplace_study(q: int, L: int, radii, steps: int, *, tau: float = 1.0, G: float = 1.3,
+                  rho_in: float = 0.96634, rho_out: float = 0.10221,
+                  precision: str = "fp64") -> dict:
+    """Static drops of several radii (Sec. 4.1, sigma = R [P_i - P_o] in 2D,
+    Delta p = 2 sigma / R in 3D).  Each drop starts from a tanh profile of the
+    coexistence densities of a flat interface at (tau, G), runs `steps` steps,
+    and gives (R_eff, Delta p).  Fits Delta p = c / R_eff + b by least squares:
+    sigma = c (2D) or c / 2 (3D), with r^2 and the intercept b."""
+    import sc_inputs
+    rows = []
+    for R in radii:
+        nz = L if q == 19 else 1
+        fl = sc_inputs.drop(L, L, nz, radius=R, rho_in=rho_in, rho_out=rho_out, width=1.0,
+                            noise=0.0)
+        lat = Lattice(q, L, L, nz, tau_A=tau, G=G, precision=precision)
+        from . import autotune
+        autotune.apply(lat)
+        lat.init(fl.rho_A, fl.rho_B)
+        lat.set_probe(*fl.centre, R)
+        lat.step(steps)
+        T = lat.totals()
+        lat.close()
+        rows.append({"R": R, "R_eff": T["R_eff"], "dp": T["dp"], "max_u": T["max_u"]})
+    x = np.array([1.0 / r["R_eff"] for r in rows])
+    y = np.array([r["dp"] for r in rows])
+    Amat = np.vstack([x, np.ones_like(x)]).T
+    (c, b), *_ = np.linalg.lstsq(Amat, y, rcond=None)
+    fit = Amat @ np.array([c, b])
+    r2 = 1.0 - ((y - fit) ** 2).sum() / ((y - y.mean()) ** 2).sum()
+    return {"rows": rows, "sigma": c / (2.0 if q == 19 else 1.0), "intercept": b, "r2": r2,
+            "max_dp": float(y.max())}
+
+
 def compare_drop(res: Dict[str, dict]) -> dict:
     a, b = res["fp64"], res["fp32_shifted"]
     ta, tb = a["totals"], b["totals"]
@@ -164,7 +197,7 @@ if __name__ == "__main__":
     import argparse
     import json
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["spinodal", "drop", "paper"])
+    ap.add_argument("study", choices=["spinodal", "drop", "paper", "laplace"])
     ap.add_argument("--L", type=int, default=None)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--every", type=int, default=500)
@@ -181,6 +214,12 @@ if __name__ == "__main__":
     elif a.study == "drop":
         r = drop_study(L=a.L or 128, steps=a.steps or 1000)
         print(json.dumps(compare_drop(r)))
+    elif a.study == "laplace":
+        r2d = laplace_study(9, 128, [10, 14, 18, 22, 26, 30], a.steps or 20000)
+        r3d = laplace_study(19, 128, [12, 16, 20, 24, 28], 4000)
+        print(json.dumps({"2d": r2d, "3d": r3d,
+                          "sigma_rel_diff": abs(r3d["sigma"] - r2d["sigma"]) / r2d["sigma"],
+                          "wall_s": time.time() - t0}))
     else:
         for prec in ("fp64", "fp32_shifted"):
             r = paper_drop_kolmogorov(prec, every=a.every)
