@@ -32,8 +32,10 @@ WORKLOAD = ("D3Q19 two-component Shan-Chen BGK 256^3 periodic, spinodal from rho
 
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+# the step kernels and the runtime that lays out their buffers (array stride):
+# recorded traffic is valid only for these exact sources
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1112_5547_amd", "csrc", f)
-                  for f in ("sc_device.h", "sc_steps.h", "sc_kernels.hip")]
+                  for f in ("sc_device.h", "sc_steps.h", "sc_kernels.hip", "sc_runtime.hip")]
 COPY_BYTES = 2 << 30  # the copy-ceiling leg moves this many bytes each way per launch
 
 

@@ -93,7 +93,8 @@ enum {
 
 /* Lattice parameters.  Validation (LBM_EINVAL otherwise):
  *   lattice in {LBM_D2Q9, LBM_D3Q19}; nx, ny, nz >= 1; nz == 1 for D2Q9;
- *   N = nx*ny*nz < 2^29 (32-bit population offsets);
+ *   N = nx*ny*nz <= 2^29 - 2112 (32-bit population offsets, array padding
+ *   included);
  *   tau_A, tau_B > 1/2 (positive viscosity c_S^2 (tau - 1/2), Sec. 2.1);
  *   G >= 0 (g_AB > 0 is the repulsive coupling, Sec. 2.1; 0 decouples);
  *   rho_ref_A, rho_ref_B: FP32_SHIFTED reference densities; a value <= 0

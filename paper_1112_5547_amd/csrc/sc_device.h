@@ -150,6 +150,7 @@ struct StepParams {
     int NX, NY, NM;     // transverse extents and march extent
     uint32_t P;         // plane size NX * NY
     uint32_t N;         // sites
+    uint32_t NS;        // elements from one population array to the next (>= N)
     int ntx, nty;       // tiles across the plane
     int nchunks, mb;    // march chunks of mb planes
     int ny_lat;         // lattice y extent (Kolmogorov forcing period)
@@ -253,6 +254,7 @@ __device__ __forceinline__ StepParams uniform_params(const StepParams& q) {
     p.NM = (int)uni32((uint32_t)q.NM);
     p.P = uni32(q.P);
     p.N = uni32(q.N);
+    p.NS = uni32(q.NS);
     p.ntx = (int)uni32((uint32_t)q.ntx);
     p.nty = (int)uni32((uint32_t)q.nty);
     p.nchunks = (int)uni32((uint32_t)q.nchunks);
@@ -558,7 +560,7 @@ struct TileStep {
         const int chunk = (int)uni32((uint32_t)chunk_in);
         const char* __restrict__ src = static_cast<const char*>(p.src);
         char* __restrict__ dst = static_cast<char*>(p.dst);
-        const uint32_t pbytes = p.N * (uint32_t)sizeof(T);  // bytes of one (s, i) array
+        const uint32_t pbytes = p.NS * (uint32_t)sizeof(T);  // (s, i) array stride in bytes
         const int tid = threadIdx.x;
         const int tx = tid % TX, ty = tid / TX;
         const int X0 = tile_x * TX, Y0 = tile_y * TY;
@@ -763,7 +765,7 @@ struct TileStepPipe {
         const int chunk = (int)uni32((uint32_t)chunk_in);
         const char* __restrict__ src = static_cast<const char*>(p.src);
         char* __restrict__ dst = static_cast<char*>(p.dst);
-        const uint32_t pbytes = p.N * (uint32_t)sizeof(T);
+        const uint32_t pbytes = p.NS * (uint32_t)sizeof(T);
         const int tid = threadIdx.x;
         const int tx = tid % TX, ty = tid / TX;
         const int X0 = tile_x * TX, Y0 = tile_y * TY;
@@ -931,7 +933,7 @@ struct TileStepRepull {
         const int chunk = (int)uni32((uint32_t)chunk_in);
         const char* __restrict__ src = static_cast<const char*>(p.src);
         char* __restrict__ dst = static_cast<char*>(p.dst);
-        const uint32_t pbytes = p.N * (uint32_t)sizeof(T);
+        const uint32_t pbytes = p.NS * (uint32_t)sizeof(T);
         const int tid = threadIdx.x;
         const int tx = tid % TX, ty = tid / TX;
         const int X0 = tile_x * TX, Y0 = tile_y * TY;

@@ -24,6 +24,7 @@ struct ObsArgs {
     double* partial;       // [nblocks][T_COUNT]
     int nx, ny, nz;
     uint32_t N;
+    uint32_t NS;           // population array stride (elements)
     double G, body_A;
     double rho_ref[2];
     int has_probe;
@@ -71,12 +72,14 @@ using BatchPersFn = void (*)(const BatchDesc*, const WorkItem*, int, int, unsign
 hipError_t launch_step(int variant, int Q, int pol, int tx, int ty, const StepParams& p,
                        void* psi, hipStream_t s);
 bool batch_kernels(int pol, int nt, int tx19, int ty19, BatchStepFn* sf, BatchPersFn* pf);
-hipError_t launch_init(int Q, int prec, void* f, const double* rho, const double* u, int nx,
-                       int ny, int nz, const double* rho_ref, hipStream_t s);
-hipError_t launch_get_plane(int Q, int prec, const void* f, double* out, int s_, int i, int nx,
-                            int ny, int nz, const double* rho_ref, hipStream_t s);
-hipError_t launch_set_plane(int Q, int prec, void* f, const double* in, int s_, int i, int nx,
-                            int ny, int nz, const double* rho_ref, hipStream_t s);
+// Population buffers hold 2Q arrays of NS >= N elements (array (s, i) at
+// element (s Q + i) NS).
+hipError_t launch_init(int Q, int prec, void* f, uint32_t NS, const double* rho, const double* u,
+                       int nx, int ny, int nz, const double* rho_ref, hipStream_t s);
+hipError_t launch_get_plane(int Q, int prec, const void* f, uint32_t NS, double* out, int s_,
+                            int i, int nx, int ny, int nz, const double* rho_ref, hipStream_t s);
+hipError_t launch_set_plane(int Q, int prec, void* f, uint32_t NS, const double* in, int s_,
+                            int i, int nx, int ny, int nz, const double* rho_ref, hipStream_t s);
 hipError_t launch_observe(int Q, int prec, const ObsArgs& a, double* totals, hipStream_t s);
 int observe_blocks(uint32_t N);
 hipError_t launch_copy(void* dst, const void* src, size_t nbytes, hipStream_t s);

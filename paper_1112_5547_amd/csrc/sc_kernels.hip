@@ -78,8 +78,8 @@ bool batch_kernels(int pol, int nt, int tx19, int ty19, BatchStepFn* sf, BatchPe
 // ---------------------------------------------------------------------------
 template <int Q, class PR>
 __global__ void __launch_bounds__(256) k_init(typename PR::T* f, const double* rho, const double* u,
-                                              int nx, int ny, int nz, uint32_t N, double rA,
-                                              double rB) {
+                                              int nx, int ny, int nz, uint32_t N, uint32_t NS,
+                                              double rA, double rB) {
     using T = typename PR::T;
     const uint32_t site = blockIdx.x * 256u + threadIdx.x;
     if (site >= N) return;
@@ -101,19 +101,19 @@ __global__ void __launch_bounds__(256) k_init(typename PR::T* f, const double* r
         for (int s = 0; s < 2; ++s) {
             const double fe = VSet<Q>::w(i) * rho[(size_t)s * N + x] * poly;
             const double val = PR::shifted ? fe - VSet<Q>::w(i) * rref[s] : fe;
-            f[(size_t)(s * Q + i) * N + site] = T(val);
+            f[(size_t)(s * Q + i) * NS + site] = T(val);
         }
     }
 }
 
-hipError_t launch_init(int Q, int prec, void* f, const double* rho, const double* u, int nx,
-                       int ny, int nz, const double* rho_ref, hipStream_t s) {
+hipError_t launch_init(int Q, int prec, void* f, uint32_t NS, const double* rho, const double* u,
+                       int nx, int ny, int nz, const double* rho_ref, hipStream_t s) {
     const uint32_t N = (uint32_t)nx * ny * nz;
     const unsigned nblk = (N + 255u) / 256u;
 #define SC_INIT(QQ, PP)                                                                      \
     hipLaunchKernelGGL((k_init<QQ, PP>), dim3(nblk), dim3(256), 0, s,                        \
-                       static_cast<typename PP::T*>(f), rho, u, nx, ny, nz, N, rho_ref[0], \
-                       rho_ref[1])
+                       static_cast<typename PP::T*>(f), rho, u, nx, ny, nz, N, NS,         \
+                       rho_ref[0], rho_ref[1])
     if (Q == 9) {
         if (prec == 0) SC_INIT(9, PF64); else SC_INIT(9, PF32S);
     } else {
@@ -124,41 +124,43 @@ hipError_t launch_init(int Q, int prec, void* f, const double* rho, const double
 }
 
 // ---------------------------------------------------------------------------
-// Population export / import of one (s, i) array, converting the pulled
-// storage to the state f(x, t) (and shifted values back to full ones).
+// Population export / import of one (s, i) array (f points at that array),
+// converting the pulled storage to the state f(x, t) (and shifted values back
+// to full ones).
 // ---------------------------------------------------------------------------
 template <int Q, class PR>
-__global__ void __launch_bounds__(256) k_get_plane(const typename PR::T* f, double* out, int s_,
-                                                   int i, int nx, int ny, int nz, uint32_t N,
+__global__ void __launch_bounds__(256) k_get_plane(const typename PR::T* f, double* out, int i,
+                                                   int nx, int ny, int nz, uint32_t N,
                                                    double shift) {
     const uint32_t site = blockIdx.x * 256u + threadIdx.x;
     if (site >= N) return;
     const SiteGeom g = site_xyz(site, nx, ny);
     const uint32_t src = site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz);
-    out[site] = (double)f[(size_t)(s_ * Q + i) * N + src] + shift;
+    out[site] = (double)f[src] + shift;
 }
 
 template <int Q, class PR>
-__global__ void __launch_bounds__(256) k_set_plane(typename PR::T* f, const double* in, int s_,
-                                                   int i, int nx, int ny, int nz, uint32_t N,
+__global__ void __launch_bounds__(256) k_set_plane(typename PR::T* f, const double* in, int i,
+                                                   int nx, int ny, int nz, uint32_t N,
                                                    double shift) {
     using T = typename PR::T;
     const uint32_t site = blockIdx.x * 256u + threadIdx.x;
     if (site >= N) return;
     const SiteGeom g = site_xyz(site, nx, ny);
     const uint32_t src = site_at(g, VSet<Q>::cx(i), VSet<Q>::cy(i), VSet<Q>::cz(i), nx, ny, nz);
-    f[(size_t)(s_ * Q + i) * N + site] = T(in[src] - shift);
+    f[site] = T(in[src] - shift);
 }
 
-hipError_t launch_get_plane(int Q, int prec, const void* f, double* out, int s_, int i, int nx,
-                            int ny, int nz, const double* rho_ref, hipStream_t s) {
+hipError_t launch_get_plane(int Q, int prec, const void* f, uint32_t NS, double* out, int s_,
+                            int i, int nx, int ny, int nz, const double* rho_ref, hipStream_t s) {
     const uint32_t N = (uint32_t)nx * ny * nz;
     const unsigned nblk = (N + 255u) / 256u;
     const double wi = Q == 9 ? VSet<9>::w(i) : VSet<19>::w(i);
     const double shift = prec == 0 ? 0.0 : wi * rho_ref[s_];
 #define SC_GET(QQ, PP)                                                                        \
     hipLaunchKernelGGL((k_get_plane<QQ, PP>), dim3(nblk), dim3(256), 0, s,                    \
-                       static_cast<const typename PP::T*>(f), out, s_, i, nx, ny, nz, N, shift)
+                       static_cast<const typename PP::T*>(f) + (size_t)(s_ * QQ + i) * NS, out,  \
+                       i, nx, ny, nz, N, shift)
     if (Q == 9) {
         if (prec == 0) SC_GET(9, PF64); else SC_GET(9, PF32S);
     } else {
@@ -168,15 +170,16 @@ hipError_t launch_get_plane(int Q, int prec, const void* f, double* out, int s_,
     return hipGetLastError();
 }
 
-hipError_t launch_set_plane(int Q, int prec, void* f, const double* in, int s_, int i, int nx,
-                            int ny, int nz, const double* rho_ref, hipStream_t s) {
+hipError_t launch_set_plane(int Q, int prec, void* f, uint32_t NS, const double* in, int s_,
+                            int i, int nx, int ny, int nz, const double* rho_ref, hipStream_t s) {
     const uint32_t N = (uint32_t)nx * ny * nz;
     const unsigned nblk = (N + 255u) / 256u;
     const double wi = Q == 9 ? VSet<9>::w(i) : VSet<19>::w(i);
     const double shift = prec == 0 ? 0.0 : wi * rho_ref[s_];
 #define SC_SET(QQ, PP)                                                                      \
     hipLaunchKernelGGL((k_set_plane<QQ, PP>), dim3(nblk), dim3(256), 0, s,                  \
-                       static_cast<typename PP::T*>(f), in, s_, i, nx, ny, nz, N, shift)
+                       static_cast<typename PP::T*>(f) + (size_t)(s_ * QQ + i) * NS, in, i,  \
+                       nx, ny, nz, N, shift)
     if (Q == 9) {
         if (prec == 0) SC_SET(9, PF64); else SC_SET(9, PF32S);
     } else {
@@ -197,7 +200,8 @@ hipError_t launch_set_plane(int Q, int prec, void* f, const double* in, int s_, 
 // ---------------------------------------------------------------------------
 template <int Q, class PR>
 __global__ void __launch_bounds__(256) k_rho64(const typename PR::T* f, double* rho, int nx, int ny,
-                                               int nz, uint32_t N, double rA, double rB) {
+                                               int nz, uint32_t N, uint32_t NS, double rA,
+                                               double rB) {
     const uint32_t site = blockIdx.x * 256u + threadIdx.x;
     if (site >= N) return;
     const SiteGeom g = site_xyz(site, nx, ny);
@@ -207,7 +211,7 @@ __global__ void __launch_bounds__(256) k_rho64(const typename PR::T* f, double* 
         double r = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            r += (double)f[(size_t)(s * Q + i) * N +
+            r += (double)f[(size_t)(s * Q + i) * NS +
                            site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)];
         rho[(size_t)s * N + site] = PR::shifted ? rref[s] + r : r;
     }
@@ -233,7 +237,7 @@ __global__ void __launch_bounds__(OBS_BLOCK) k_observe(ObsArgs a) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const double fv =
-                    (double)f[(size_t)(s * Q + i) * N +
+                    (double)f[(size_t)(s * Q + i) * a.NS +
                               site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), a.nx,
                                       a.ny, a.nz)];
                 j[0] += VSet<Q>::cx(i) * fv;
@@ -353,7 +357,7 @@ hipError_t launch_observe(int Q, int prec, const ObsArgs& a, double* totals, hip
     do {                                                                                        \
         hipLaunchKernelGGL((k_rho64<QQ, PP>), dim3(nblk), dim3(256), 0, s,                      \
                            static_cast<const typename PP::T*>(a.f), rho, a.nx, a.ny, a.nz, a.N, \
-                           a.rho_ref[0], a.rho_ref[1]);                                         \
+                           a.NS, a.rho_ref[0], a.rho_ref[1]);                                   \
         hipLaunchKernelGGL((k_observe<QQ, PP>), dim3(nblk), dim3(OBS_BLOCK), 0, s, a);          \
     } while (0)
     if (Q == 9) {

@@ -19,6 +19,7 @@ struct lbm_sc {
     lbm_sc_params p{};
     int Q = 0;
     uint32_t N = 0;
+    uint32_t NS = 0;  // population array stride (elements), >= N
     int device = 0;
     char* mem = nullptr;
     bool own_mem = false;
@@ -58,6 +59,7 @@ inline int sc_policy(const lbm_sc_params& p) {
 }
 
 Layout sc_layout(const lbm_sc_params* p);
+uint32_t sc_array_stride(const lbm_sc_params* p);
 void sc_default_kernel(int Q, int nx, int ny, int nz, int* tx, int* ty, int* mb);
 sc::StepParams sc_step_params(const lbm_sc* h, int parity);
 hipError_t sc_launch_step(lbm_sc* h, int parity, hipStream_t s);

@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(256) k_density(StepParams p, typename PR::A* p
         A r = A(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            r += A(f[(size_t)(s * Q + i) * p.N +
+            r += A(f[(size_t)(s * Q + i) * p.NS +
                      site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)]);
         psi[(size_t)s * p.N + site] = r;
     }
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(256) k_collide2(StepParams p, const typename P
     for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            v[s][i] = f[(size_t)(s * Q + i) * p.N +
+            v[s][i] = f[(size_t)(s * Q + i) * p.NS +
                         site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)];
     A gs[2][3];
     gather<Q>([&](int s, int i) {
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) k_collide2(StepParams p, const typename P
                    site_at(g, VSet<Q>::cx(i), VSet<Q>::cy(i), VSet<Q>::cz(i), nx, ny, nz)];
     }, gs);
     const double body = p.body_A != 0.0 ? kolmogorov(p, g.y) : 0.0;
-    collide_store<Q, PR>(v, gs, p, body, static_cast<char*>(p.dst), p.N * (uint32_t)sizeof(T),
+    collide_store<Q, PR>(v, gs, p, body, static_cast<char*>(p.dst), p.NS * (uint32_t)sizeof(T),
                          site * (uint32_t)sizeof(T), 0u);
 }
 

@@ -90,6 +90,44 @@ def test_params_validation_and_sizes():
         assert L.lbm_sc_bytes_needed(ctypes.byref(q)) == 0
 
 
+def _pop_bytes(q, nx, ny, nz, es):
+    """Population bytes of a handle (both buffers), from its total minus the
+    side arrays (psi 2N es, rho 2N 8, u 3N 8, reduction partials)."""
+    from paper_1112_5547_amd import _abi
+    p = _abi.Params()
+    assert _lib().lbm_sc_params_default(ctypes.byref(p), q, nx, ny, nz, 1.0, 1.0, 1.0) == 0
+    if es == 4:
+        p.precision = _abi.LBM_FP32_SHIFTED
+    return int(_lib().lbm_sc_bytes_needed(ctypes.byref(p)))
+
+
+def test_population_arrays_are_padded_and_aligned():
+    """Each of the 2Q arrays of a buffer spans N rounded up to 32 elements,
+    plus 2080 elements from 2^16 sites on (staggers power-of-two strides
+    across HBM channels).  Checked through bytes_needed as N grows."""
+    for q, es in ((9, 8), (19, 4)):
+        nz = 1 if q == 9 else 2
+        b32, b33, b34 = (_pop_bytes(q, n, 1, nz, es) for n in (32, 33, 34))
+        block = 2 * 2 * q * 32 * es        # both buffers, 2Q arrays, 32 more elements
+        side = 6 * 256                     # side arrays grow by at most one alignment unit each
+        # N = 32 nz -> 33 nz crosses a 32-element boundary: every array grows by 32
+        assert block <= b33 - b32 <= block + side
+        # 33 nz -> 34 nz stays inside it (N = 66 -> 68 for D3Q19 still rounds to 96)
+        assert b34 - b33 <= side
+    # the padding switches on at 2^16 sites
+    below = _pop_bytes(9, 65535, 1, 1, 8)
+    at = _pop_bytes(9, 65536, 1, 1, 8)
+    assert at - below >= 2 * 2 * 9 * 2080 * 8
+    # largest lattice whose padded arrays keep 32-bit byte offsets
+    from paper_1112_5547_amd import _abi
+    L = _lib()
+    for n, ok in ((2 ** 29 - 2112, True), (2 ** 29 - 2111, False)):
+        p = _abi.Params()
+        rc = L.lbm_sc_params_default(ctypes.byref(p), 9, n, 1, 1, 1.0, 1.0, 1.0)
+        assert (rc == 0) == ok, n
+        assert (L.lbm_sc_bytes_needed(ctypes.byref(p)) > 0) == ok
+
+
 def test_tile_tables_and_strerror():
     L = _lib()
     for q in (9, 19):
