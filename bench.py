@@ -39,6 +39,11 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1112_5547_amd", "csrc", f)
 COPY_BYTES = 2 << 30  # the copy-ceiling leg moves this many bytes each way per launch
 
 
+def progress(msg: str):
+    """One line on stderr as each leg of the run ends (stdout keeps the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_sources_sha() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -214,6 +219,7 @@ def serve_leg(n_jobs: int, budget_gb: float, epoch: int):
     probe = sc_inputs.serving_jobs(n_jobs, seed=5, rate=1.0)
     step_s = solo_step_seconds(probe, GpuBackend("fp32_shifted"))
     capacity = solo_capacity(probe, step_s)
+    progress(f"serving: solo capacity {capacity:.0f} MLUPS")
     rate = offered_rate(probe, capacity, load=0.7)
     jobs = sc_inputs.serving_jobs(n_jobs, seed=5, rate=rate)
     # batch tiles for the job mix, timed on the 8 smallest jobs of each lattice type
@@ -225,6 +231,7 @@ def serve_leg(n_jobs: int, budget_gb: float, epoch: int):
                     aging=0.25, nominal_rate=capacity * 1e6)
     rep = server.run(jobs)
     served = rep.summary()
+    progress(f"serving: served stream p50 {served['p50_latency_s']:.2f} s")
     seq = sequential_baseline(jobs, backend=GpuBackend("fp32_shifted"))
     r3 = lambda v: round(v, 3) if isinstance(v, float) else v
     return {"workload": f"{n_jobs} Poisson jobs (seed 5), 70% D2Q9 64^2-512^2 drops, 30% D3Q19 "
@@ -281,6 +288,7 @@ def main():
     ach = b_alg(Q19, 8) * n / (r64["kernel_ms"] * 1e-3) / 1e9
     sym64 = kernel_symbol(r64["kernel"], "fp64")
     traffic64, tbytes64 = traffic_for(sym64, r64["kernel_ms"])
+    progress(f"fp64 step {r64['kernel_ms']:.4f} ms")
     out = {
         "metric": "MLUPS + % HBM roofline, D3Q19 2-comp SC 256^3; served-job p50/p99 latency",
         "value": round(mlups, 1),
@@ -310,6 +318,7 @@ def main():
         ach32 = b_alg(Q19, 4) * n / (r32["kernel_ms"] * 1e-3) / 1e9
         sym32 = kernel_symbol(r32["kernel"], "fp32_shifted")
         traffic32, tbytes32 = traffic_for(sym32, r32["kernel_ms"])
+        progress(f"fp32_shifted step {r32['kernel_ms']:.4f} ms")
         out["fp32_shifted"] = {
             "value": round(n * args.steps / r32["wall_s"] / 1e6, 1), "unit": "MLUPS",
             "ms_per_step": round(r32["wall_s"] * 1e3 / args.steps, 4),
@@ -343,15 +352,19 @@ def main():
                     "kernel": list(rg["kernel"]),
                     "mass_drift_A": (rg["T"]["mass_A"] - rg["T0"]["mass_A"]) / rg["T0"]["mass_A"],
                 }
+                progress(f"{scheme} {prec} step {rg['kernel_ms']:.4f} ms")
     if not args.no_batch:
         out["batched"] = batch_leg(64, args.batch_steps, epoch=250)
+        progress("batch leg done")
     if not args.no_serve:
         out["served"] = serve_leg(args.serve_jobs, budget_gb=96.0, epoch=250)
         out["metric_served"] = {"p50_latency_s": out["served"]["served"]["p50_latency_s"],
                                 "p99_latency_s": out["served"]["served"]["p99_latency_s"],
                                 "aggregate_mlups": out["served"]["served"]["aggregate_mlups"]}
+        progress("serving leg done")
     if not args.no_copy:
         out["copy_ceiling_GBps"] = round(copy_bench(COPY_BYTES, reps=10), 1)
+        progress(f"copy ceiling {out['copy_ceiling_GBps']} GB/s")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(fields)
     print(json.dumps(out), flush=True)
