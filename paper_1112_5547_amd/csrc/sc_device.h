@@ -468,10 +468,17 @@ __device__ __forceinline__ void collide_store(const typename PR::T (&f)[2][Q],
         }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            A F[3];
+            A F[3], us[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) F[a] = rfull[s] * acc[s][a];
-            relax_store<Q, PR>(f[s], s, u, F, rho[s], rfull[s], om[s], omm[s], dst, pbytes, voff,
+            for (int a = 0; a < 3; ++a) {
+                F[a] = rfull[s] * acc[s][a];
+                // an opaque copy per species: keeps the compiler from sharing the
+                // c_i.u terms of the two species, whose values would stay live
+                // across the first species' relaxation and overflow the registers
+                us[a] = u[a];
+                asm volatile("" : "+v"(us[a]));
+            }
+            relax_store<Q, PR>(f[s], s, us, F, rho[s], rfull[s], om[s], omm[s], dst, pbytes, voff,
                                soff);
         }
     } else {

@@ -62,6 +62,27 @@ def test_d3q19_ragged_tiles_and_variants(kernel):
     assert maxabs(f, ref) <= TOL
 
 
+@pytest.mark.parametrize("q,shape,kernel", [
+    (19, (40, 43, 41), (0, 64, 8, 16)), (19, (40, 43, 41), (2, 32, 8, 7)),
+    (19, (40, 43, 41), (1, 32, 4, 8)), (9, (1, 251, 263), (2, 256, 1, 9)),
+    (9, (1, 251, 263), (3, 128, 1, 5))])
+def test_padded_array_stride_ragged(q, shape, kernel):
+    """Lattices of more than 2^16 sites whose N is not a multiple of 32: the
+    population arrays are N rounded up to 32 plus 2080 elements apart, so
+    every array base other than the first is offset from N * (s Q + i)."""
+    nz, ny, nx = shape
+    assert nx * ny * nz >= 1 << 16 and (nx * ny * nz) % 32 != 0
+    if q == 19:
+        fl = sc_inputs.spinodal(nx, ny, nz, seed=21)
+    else:
+        fl = sc_inputs.drop(nx, ny, 1, radius=40, seed=21)
+    steps = 12 if q == 19 else 40
+    say(f"padded stride q={q} shape={shape} kernel={kernel}, {steps} steps")
+    _, f = gpu_run(q, fl.rho_A, fl.rho_B, 0.9, 1.2, 1.5, steps, kernel=kernel, body_A=1e-4)
+    ref = oracle_run(q, fl.rho_A, fl.rho_B, 0.9, 1.2, 1.5, steps, body_A=1e-4)
+    assert maxabs(f, ref) <= TOL
+
+
 @pytest.mark.parametrize("q,shape", [(9, (1, 5, 1)), (9, (1, 1, 7)), (9, (1, 2, 3)),
                                      (19, (6, 1, 1)), (19, (1, 4, 5)), (19, (2, 3, 2)),
                                      (19, (1, 1, 1))])
