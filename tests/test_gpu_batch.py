@@ -19,6 +19,9 @@ SPECS = [  # (q, nx, ny, nz, tau, G, steps, kind)
     (19, 24, 20, 18, 1.0, 1.6, 45, "spinodal"),
     (9, 33, 200, 1, 1.2, 1.25, 50, "drop"),
     (19, 16, 16, 16, 0.9, 1.3, 21, "drop"),
+    # above 2^16 sites with N not a multiple of 32: padded array strides
+    (9, 300, 230, 1, 0.8, 1.4, 23, "drop"),
+    (19, 42, 41, 40, 1.1, 1.5, 9, "spinodal"),
 ]
 
 
