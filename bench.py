@@ -222,10 +222,14 @@ def serve_leg(n_jobs: int, budget_gb: float, epoch: int):
     progress(f"serving: solo capacity {capacity:.0f} MLUPS")
     rate = offered_rate(probe, capacity, load=0.7)
     jobs = sc_inputs.serving_jobs(n_jobs, seed=5, rate=rate)
-    # batch tiles for the job mix, timed on the 8 smallest jobs of each lattice type
+    # batch tile shape for the job mix, timed on the 8 smallest jobs of each
+    # lattice type; the march chunks stay each lattice's own tuned chunk (a
+    # chunk tuned on the smallest jobs alone can be a single-chunk march that
+    # leaves the large members a few long work items per step)
     sample = (sorted([j for j in jobs if j.lattice == 9], key=lambda j: j.sites)[:8]
               + sorted([j for j in jobs if j.lattice == 19], key=lambda j: j.sites)[:8])
-    tiles = autotune.tune_batch(sample, precision="fp32_shifted", mode="fused", epoch=20)
+    tiles = autotune.tune_batch(sample, precision="fp32_shifted", mode="fused", epoch=20,
+                                mbs=(0,))
     server = Server(hbm_budget=int(budget_gb * 1e9), epoch_steps=epoch, mode="fused",
                     backend=GpuBackend("fp32_shifted"), tiles=tiles, policy="srpt",
                     aging=0.25, nominal_rate=capacity * 1e6)

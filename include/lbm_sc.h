@@ -204,13 +204,17 @@ int lbm_sc_sync(lbm_sc *h);
  * and returns the elapsed milliseconds of those n steps in *ms. */
 int lbm_sc_time_steps(lbm_sc *h, int n, float *ms);
 
-/* Kernel configuration.  variant: 0 = fused single-kernel step (default),
- * 1 = two kernels per step (densities, then collide), 2 = fused step with a
+/* Kernel configuration.  variant: 0 = fused single-kernel step, 1 = two
+ * kernels per step (densities, then collide), 2 = fused step with a
  * three-plane register pipeline (loads of plane m+2 overlap the collision of
  * plane m), 3 = fused step holding no plane across iterations (plane m is
  * pulled again, from cache, for its collision).  tx, ty: transverse
  * tile (ty = 1 on D2Q9); mb: sites marched per block along the slowest axis
- * (y on D2Q9, z on D3Q19).  Unsupported tiles return LBM_EINVAL. */
+ * (y on D2Q9, z on D3Q19).  Unsupported tiles return LBM_EINVAL.  A new
+ * handle starts with variant 0 on D2Q9; on D3Q19 with 64 x 8 tiles (32 x 4
+ * for nx <= 32), variant 0 in FP64 and 2 in FP32_SHIFTED, and march chunks
+ * of about one block per compute unit.  Every configuration computes the same
+ * result bit for bit. */
 int lbm_sc_set_kernel(lbm_sc *h, int variant, int tx, int ty, int mb);
 int lbm_sc_get_kernel(const lbm_sc *h, int *variant, int *tx, int *ty, int *mb);
 

@@ -60,7 +60,7 @@ inline int sc_policy(const lbm_sc_params& p) {
 
 Layout sc_layout(const lbm_sc_params* p);
 uint32_t sc_array_stride(const lbm_sc_params* p);
-void sc_default_kernel(int Q, int nx, int ny, int nz, int* tx, int* ty, int* mb);
+void sc_default_kernel(const lbm_sc_params* p, int* variant, int* tx, int* ty, int* mb);
 sc::StepParams sc_step_params(const lbm_sc* h, int parity);
 hipError_t sc_launch_step(lbm_sc* h, int parity, hipStream_t s);
 int sc_enqueue_steps(lbm_sc* h, long long n, hipStream_t s);

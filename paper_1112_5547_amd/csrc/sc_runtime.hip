@@ -104,8 +104,17 @@ Layout sc_layout(const lbm_sc_params* p) {
 // Default kernel configuration: tile width close to the x extent, march chunk
 // sized for about four waves of blocks on 256 CUs (at least 8 planes so the two
 // extra density planes per chunk stay a small overhead).
-void sc_default_kernel(int Q, int nx, int ny, int nz, int* tx, int* ty, int* mb) {
+// Kernel configuration of a new handle, the choice the autotuner made for the
+// tuned lattices.  D2Q9: the fused march on a row tile of up to 256 sites,
+// march chunks giving about 1024 blocks.  D3Q19: 64 x 8 tiles (32 x 4 for
+// nx <= 32), the fused march in FP64 and the pipelined one in FP32 shifted
+// (whose three register planes fit at two waves per SIMD), march chunks giving
+// about one block per CU (256); at 128^3 and 256^3 this is exactly the tuned
+// configuration of both precisions.
+void sc_default_kernel(const lbm_sc_params* p, int* variant, int* tx, int* ty, int* mb) {
+    const int Q = p->lattice, nx = p->nx, ny = p->ny, nz = p->nz;
     if (Q == 9) {
+        *variant = 0;
         *tx = nx <= 64 ? 64 : (nx <= 128 ? 128 : 256);
         *ty = 1;
         const int ntx = (nx + *tx - 1) / *tx;
@@ -114,11 +123,13 @@ void sc_default_kernel(int Q, int nx, int ny, int nz, int* tx, int* ty, int* mb)
         int m = (NM + chunks - 1) / chunks;
         *mb = std::max(std::min(m, NM), std::min(8, NM));
     } else {
-        *tx = nx <= 32 ? 32 : 64;
-        *ty = 4;
+        const bool small = nx <= 32;
+        *variant = p->precision == LBM_FP32_SHIFTED ? 2 : 0;
+        *tx = small ? 32 : 64;
+        *ty = small ? 4 : 8;
         const int tiles = ((nx + *tx - 1) / *tx) * ((ny + *ty - 1) / *ty);
         const int NM = nz;
-        int chunks = std::max(1, 1024 / tiles);
+        int chunks = std::max(1, 256 / tiles);
         int m = (NM + chunks - 1) / chunks;
         *mb = std::max(std::min(m, NM), std::min(8, NM));
     }
@@ -350,8 +361,7 @@ int lbm_sc_create_ex(lbm_sc** out, const lbm_sc_params* p, void* stream, void* a
         delete h;
         return LBM_EDEVICE;
     }
-    h->variant = 0;
-    sc_default_kernel(h->Q, p->nx, p->ny, p->nz, &h->tx, &h->ty, &h->mb);
+    sc_default_kernel(p, &h->variant, &h->tx, &h->ty, &h->mb);
     h->rho_ref[0] = p->rho_ref_A;
     h->rho_ref[1] = p->rho_ref_B;
     *out = h;

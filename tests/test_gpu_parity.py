@@ -62,6 +62,21 @@ def test_d3q19_ragged_tiles_and_variants(kernel):
     assert maxabs(f, ref) <= TOL
 
 
+def test_default_kernel_configuration():
+    """A new handle starts with the documented configuration: D3Q19 64 x 8
+    tiles (32 x 4 for nx <= 32), fused in FP64, pipelined in FP32 shifted,
+    march chunks of about one block per compute unit."""
+    from paper_1112_5547_amd import Lattice
+    cases = [((19, 128, 128, 128, "fp64"), (0, 64, 8, 16)),
+             ((19, 128, 128, 128, "fp32_shifted"), (2, 64, 8, 16)),
+             ((19, 32, 32, 32, "fp64"), (0, 32, 4, 8)),
+             ((9, 1024, 1024, 1, "fp64"), (0, 256, 1, 8))]
+    for (q, nx, ny, nz, prec), expect in cases:
+        lat = Lattice(q, nx, ny, nz, tau_A=1.0, G=1.3, precision=prec)
+        assert lat.kernel == expect, (q, nx, ny, nz, prec, lat.kernel)
+        lat.close()
+
+
 @pytest.mark.parametrize("q,shape,kernel", [
     (19, (40, 43, 41), (0, 64, 8, 16)), (19, (40, 43, 41), (2, 32, 8, 7)),
     (19, (40, 43, 41), (1, 32, 4, 8)), (9, (1, 251, 263), (2, 256, 1, 9)),
