@@ -163,9 +163,10 @@ def cpu_baseline(fields):
 
 def batch_leg(n_jobs: int, steps: int, epoch: int):
     """64 independent D2Q9 drop lattices (L ~ U{64..512}, seed 4), FP32 shifted,
-    advanced `steps` steps each: one launch per lattice per step, one launch per
-    step for all lattices (graph-replayed), and one persistent launch per epoch,
-    after the batch autotuner picked the block shape and march chunks."""
+    advanced `steps` steps each: one launch per lattice per step (each lattice
+    with its own autotuned kernel), one launch per step for all lattices
+    (graph-replayed), and one persistent launch per epoch, after the batch
+    autotuner picked the block shape and march chunks."""
     import torch
     import sc_inputs
     from paper_1112_5547_amd import Batch, Lattice, autotune
@@ -179,6 +180,8 @@ def batch_leg(n_jobs: int, steps: int, epoch: int):
         lats = []
         for j in jobs:
             lat = Lattice(9, j.nx, j.ny, 1, tau_A=j.tau, G=j.G, precision="fp32_shifted")
+            if mode == "per_lattice":
+                autotune.apply(lat)
             fl = j.fields()
             lat.init(fl.rho_A, fl.rho_B)
             lats.append(lat)
