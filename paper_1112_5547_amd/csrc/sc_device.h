@@ -515,16 +515,6 @@ struct TileStep {
         return ((slot * 2 + s) * FH + fy) * FW + fx;
     }
 
-    // True for waves whose tile rows are all at least two rows from the
-    // tile's y edges: no neighbouring tile's ring pulls read their sites, so
-    // their loads stream (nontemporal) and leave L2 to the boundary rows.
-    __device__ static __forceinline__ bool streaming_wave() {
-        if (!HY || TY < 5) return false;
-        const int w0 = (int)(threadIdx.x & ~63u);
-        const int ty_lo = w0 / TX, ty_hi = (w0 + 63) / TX;
-        return ty_lo >= 2 && ty_hi <= TY - 3;
-    }
-
     // Pull the 2Q populations of one site of plane m into v and return the
     // two species' density sums (delta densities when shifted).  pb holds the
     // byte offsets of planes m-1, m, m+1 (uniform across the block) and off
@@ -627,7 +617,6 @@ struct TileStep {
         T cur[2][Q], nxt[2][Q];
         A dA, dB;
         uint32_t pb[3];
-        const bool stream = streaming_wave();
 
         auto plane_bases = [&](int m) {
             const int mm = wrapi(m, NM);
@@ -649,10 +638,10 @@ struct TileStep {
             // keep the ring's loads from overlapping the plane kept in
             // registers: bounds the live registers to two planes
             __builtin_amdgcn_sched_barrier(0);
-            if (stream)
-                pull<2>(src, pbytes, pb, off, nxt, dA, dB);
-            else
-                pull<0>(src, pbytes, pb, off, nxt, dA, dB);
+            // default cache policy: streaming (nontemporal) loads for the rows
+            // no neighbouring tile re-reads measured 1.3 % slower on the
+            // padded layout
+            pull<0>(src, pbytes, pb, off, nxt, dA, dB);
             lds[lidx(slot, 0, own_fy, own_fx)] = dA;
             lds[lidx(slot, 1, own_fy, own_fx)] = dB;
         };
