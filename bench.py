@@ -9,8 +9,8 @@ Prints one JSON line: MLUPS of the FP64 step (value), its HBM roofline
 fraction from algorithmic bytes (2 species x 19 populations x read+write x
 8 B = 608 B per site update) over the step kernel's average duration timed
 with HIP events on the lattice's stream, the FP32-shifted step's figures, a
-streaming-copy ceiling, and the FP64 CPU oracle timed on the host on one step
-of the same lattice.
+streaming-copy ceiling, and the FP64 CPU oracle timed on the host on the
+same lattice (all cores and one thread) and on the full 64^2 D2Q9 drop run.
 """
 from __future__ import annotations
 
@@ -147,18 +147,56 @@ def time_lattice(fields, precision, steps, warmup, kernel=None, forcing="shift",
     return {"wall_s": wall, "kernel_ms": ms_events / steps, "T0": T0, "T": T, "kernel": kern}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(fields):
-    """The FP64 oracle (plain C, one thread) on one step of the same lattice."""
+    """The FP64 oracle (plain C, -O2, no FMA contraction) timed on the host:
+    the same source built with OpenMP over lattice planes on every core this
+    process may use (the headline value), one thread, and the full 2000-step
+    run of the 64^2 D2Q9 drop."""
     import oracle
+    import sc_inputs
+    host_cores = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS") or host_cores)
+    os.environ["OMP_NUM_THREADS"] = str(threads)
     oracle.build(force=False)
+    n = L ** 3
     f0 = oracle.init(Q19, fields.rho_A, fields.rho_B)
+    steps_mt = 2
+    t0 = time.perf_counter()
+    oracle.run(f0, TAU, TAU, G, steps_mt, all_cores=True)
+    dt_mt = time.perf_counter() - t0
     t0 = time.perf_counter()
     oracle.run(f0, TAU, TAU, G, 1)
-    dt = time.perf_counter() - t0
-    n = L ** 3
-    return {"value": n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"1 full time step of the 256^3 D3Q19 lattice ({n} site updates, "
-                      f"{dt:.1f} s, single-threaded C oracle, -O2, no FMA contraction)"}
+    dt_1 = time.perf_counter() - t0
+    del f0
+    fl = sc_inputs.drop(64, 64, 1, radius=16, rho_in=1.0, rho_out=0.05, noise=1e-3, seed=1)
+    g0 = oracle.init(9, fl.rho_A, fl.rho_B)
+    t0 = time.perf_counter()
+    oracle.run(g0, 1.0, 1.0, 1.3, 2000)
+    dt_cfg1 = time.perf_counter() - t0
+    return {"value": round(n * steps_mt / dt_mt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps_mt} full time steps of the 256^3 D3Q19 lattice "
+                      f"({n * steps_mt} site updates, {dt_mt:.1f} s) on {threads} OpenMP threads "
+                      "(the C oracle, -O2, no FMA contraction, per-site loops shared over "
+                      "lattice planes)",
+            "host_cores": host_cores, "cpu_model": cpu_model(),
+            "single_thread": {"value": round(n / dt_1 / 1e6, 3), "unit": "MLUPS",
+                              "sample": f"1 full time step of the 256^3 lattice, {dt_1:.1f} s"},
+            "cfg1_full_run": {"seconds": round(dt_cfg1, 3), "threads": 1,
+                              "workload": "D2Q9 64x64 drop R=16, tau=1, G=1.3, 2000 steps "
+                                          "(8.19M site updates)",
+                              "mlups": round(64 * 64 * 2000 / dt_cfg1 / 1e6, 3)}}
 
 
 def batch_leg(n_jobs: int, steps: int, epoch: int):

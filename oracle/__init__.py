@@ -27,6 +27,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_sc.so")
+# the same source built with OpenMP: used only to time the oracle on all host cores
+_LIB_OMP = os.path.join(_HERE, "liboracle_sc_omp.so")
 
 # totals layout of oracle_observables
 TOTAL_KEYS = ("mass_A", "mass_B", "mom_x", "mom_y", "mom_z", "max_u", "p_in", "p_out",
@@ -35,26 +37,39 @@ TOTAL_KEYS = ("mass_A", "mass_B", "mom_x", "mom_y", "mom_z", "max_u", "p_in", "p
 CS2 = 1.0 / 3.0
 
 
+_CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-D_DEFAULT_SOURCE",
+           "-fPIC", "-shared", "-Wall"]
+
+
+def _stale(path: str) -> bool:
+    return not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC)
+
+
 def build(force: bool = True) -> str:
-    """Compile the C oracle (gcc, -O2, no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the C oracle (gcc, -O2, no FMA contraction, no fast-math): the
+    single-threaded library every check uses, and the same source with OpenMP
+    for the all-core timing of the CPU baseline."""
+    if force or _stale(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-                               "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-Wall", "-o", tmp,
-                               _SRC, "-lm"])
+        subprocess.check_call(["gcc", *_CFLAGS, "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
+    if force or _stale(_LIB_OMP):
+        tmp = _LIB_OMP + ".tmp"
+        subprocess.check_call(["gcc", *_CFLAGS, "-fopenmp", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_OMP)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+def lib(all_cores: bool = False):
+    """The single-threaded oracle library, or its OpenMP build (all_cores)."""
+    path = _LIB_OMP if all_cores else _LIB
+    if path not in _libs:
+        if _stale(path):
             build(force=True)
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         lp = ctypes.POINTER(ctypes.c_long)
@@ -73,8 +88,8 @@ def lib():
                    "oracle_force", "oracle_collide", "oracle_stream", "oracle_run",
                    "oracle_observables", "oracle_step_sites"):
             getattr(L, fn).restype = ctypes.c_int
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _p(a: Optional[np.ndarray]):
@@ -182,12 +197,14 @@ def stream(fpost: np.ndarray) -> np.ndarray:
 
 
 def run(f: np.ndarray, tau_A: float, tau_B: float, G: float, steps: int,
-        body_A: float = 0.0, forcing: str = "shift", tau_minus=None) -> np.ndarray:
-    """``steps`` full collide+stream steps; returns a new array."""
+        body_A: float = 0.0, forcing: str = "shift", tau_minus=None,
+        all_cores: bool = False) -> np.ndarray:
+    """``steps`` full collide+stream steps; returns a new array.  all_cores runs
+    the OpenMP build of the same source (same result bit for bit; for timing)."""
     q = f.shape[1]
     nx, ny, nz = _dims(f.shape[2:])
     g = np.array(f, dtype=np.float64, order="C", copy=True)
-    _check(lib().oracle_run(q, nx, ny, nz, tau_A, tau_B, G, body_A, _p(g), steps,
+    _check(lib(all_cores).oracle_run(q, nx, ny, nz, tau_A, tau_B, G, body_A, _p(g), steps,
                             _forcing(forcing), *_taum(tau_minus)), "run")
     return g
 

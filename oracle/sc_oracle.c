@@ -14,7 +14,10 @@
  * Everything is written the slow and obvious way: one loop per step of the
  * method, in the paper's order and notation, double precision throughout, no
  * blocking or fusion.  Built with -O2 -ffp-contract=off (no fused multiply-add,
- * no fast-math).
+ * no fast-math).  The per-site loops carry OpenMP pragmas: the default build
+ * ignores them (one thread); the all-core build used only to time the oracle
+ * on the host runs the same per-site arithmetic, with the sites of a loop
+ * shared out among threads (no reductions, so the results are bitwise equal).
  *
  * Layout of a population array f: f[s][i][z][y][x], x fastest, species s in
  * {A=0, B=1}, velocity i in [0, Q).  N = nx*ny*nz sites.  The state held
@@ -166,6 +169,7 @@ int oracle_moments(int q, int nx, int ny, int nz, const double *f, double *rho, 
     lat_t L;
     if (lat_make(&L, q, nx, ny, nz) != 0) return -1;
     for (int s = 0; s < 2; ++s) {
+#pragma omp parallel for schedule(static)
         for (long x = 0; x < L.n; ++x) {
             double r = 0.0, ja[3] = {0.0, 0.0, 0.0};
             for (int i = 0; i < q; ++i) {
@@ -188,6 +192,7 @@ int oracle_moments(int q, int nx, int ny, int nz, const double *f, double *rho, 
 int oracle_force(int q, int nx, int ny, int nz, double G, const double *rho, double *F) {
     lat_t L;
     if (lat_make(&L, q, nx, ny, nz) != 0) return -1;
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -332,11 +337,12 @@ int oracle_collide(int q, int nx, int ny, int nz, double tauA, double tauB, doub
     oracle_force(q, nx, ny, nz, G, rho, F); /* psi_s = rho_s */
     const double taup[2] = {tauA, tauB};
     const double taum[2] = {tmA > 0.0 ? tmA : tauA, tmB > 0.0 ? tmB : tauB};
-    double fin[38], fout[38];
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long site = ((long)z * ny + y) * nx + x;
+                double fin[38], fout[38];
                 double r[2], js[2][3], Fs[2][3];
                 for (int s = 0; s < 2; ++s) {
                     r[s] = rho[s * L.n + site];
@@ -364,6 +370,7 @@ int oracle_stream(int q, int nx, int ny, int nz, const double *fpost, double *fn
     if (lat_make(&L, q, nx, ny, nz) != 0) return -1;
     for (int s = 0; s < 2; ++s)
         for (int i = 0; i < q; ++i)
+#pragma omp parallel for schedule(static)
             for (int z = 0; z < nz; ++z)
                 for (int y = 0; y < ny; ++y)
                     for (int x = 0; x < nx; ++x) {
