@@ -230,3 +230,17 @@ def test_linear_phi_rate_matches_paper_continuum_limit(rho, tau, G):
     kk = 0.02
     assert abs(lt.phi_mode_rate(9, (kk, 0, 0), rho, tau, G).real
                - lt.paper_phi_rate(kk, rho, tau, G)) < 0.01 * abs(a) * kk**2
+
+
+@pytest.mark.parametrize("q,shape,forcing,tm", [(9, (1, 40, 36), "shift", None),
+                                                (19, (10, 12, 14), "guo", None),
+                                                (19, (9, 8, 7), "shift", (0.8, 1.3))])
+def test_all_core_build_equals_single_thread(q, shape, forcing, tm):
+    """The OpenMP build of the oracle (used to time it on all host cores) runs
+    the same per-site arithmetic: its populations equal the default build's."""
+    fl = sc_inputs.drop(shape[2], shape[1], shape[0], radius=min(shape[1:]) / 4, seed=9)
+    f0 = oracle.init(q, fl.rho_A, fl.rho_B)
+    a = oracle.run(f0, 0.9, 1.1, 1.4, 12, body_A=1e-5, forcing=forcing, tau_minus=tm)
+    b = oracle.run(f0, 0.9, 1.1, 1.4, 12, body_A=1e-5, forcing=forcing, tau_minus=tm,
+                   all_cores=True)
+    assert np.array_equal(a, b)
