@@ -268,7 +268,10 @@ int lbm_batch_create(lbm_batch **out, size_t hbm_budget, void *stream);
  * batch.  The batch does not own the handle. */
 int lbm_batch_add(lbm_batch *b, lbm_sc *h, long long steps);
 
-/* Removes a member (finished or not).  The handle stays valid. */
+/* Removes a member (finished or not).  The handle stays valid.  Waits for the
+ * batch's stream; returns LBM_ETIMEOUT (after removing the member) if a
+ * persistent launch of the batch gave up at a grid barrier (see
+ * lbm_batch_poll). */
 int lbm_batch_remove(lbm_batch *b, lbm_sc *h);
 
 /* Enqueues up to epoch_steps steps of every member with steps remaining.
@@ -277,7 +280,13 @@ int lbm_batch_run(lbm_batch *b, int epoch_steps, int mode);
 
 /* Waits for the batch's stream, then writes up to max_done members whose
  * steps are complete into done[] and their count into *n_done (finished
- * members stay in the batch until removed). */
+ * members stay in the batch until removed).  Returns LBM_ETIMEOUT if a
+ * persistent launch gave up at a grid barrier (its blocks waited longer than
+ * the spin limit for the others, e.g. because they were not co-resident):
+ * every block then leaves the kernel, the members are left part way through
+ * the epoch, the batch is failed and each member handle accepts only removal
+ * and lbm_sc_destroy.  The flag that reports it survives later launches until
+ * the host has read it here, in lbm_batch_remove or in lbm_batch_destroy. */
 int lbm_batch_poll(lbm_batch *b, lbm_sc **done, int max_done, int *n_done);
 
 /* Members, bytes in use and pending site-updates of the batch. */
@@ -288,6 +297,14 @@ int lbm_batch_stats(const lbm_batch *b, int *members, size_t *bytes_used,
  * persistent batch launches (0 keeps the default). */
 int lbm_batch_set_tiles(lbm_batch *b, int tx9, int tx19, int ty19, int mb9, int mb19);
 
+/* Grid-barrier polls (each a short sleep) a block of a persistent launch
+ * makes before it gives up and the launch reports LBM_ETIMEOUT; 0 restores
+ * the default (2^26, seconds).  A small value forces the give-up path. */
+int lbm_batch_set_spin_limit(lbm_batch *b, unsigned spins);
+
+/* Releases the batch (its members stay valid and leave it).  Waits for its
+ * stream; returns LBM_ETIMEOUT if an unreported persistent-launch give-up is
+ * found, LBM_OK otherwise. */
 int lbm_batch_destroy(lbm_batch *b);
 
 #ifdef __cplusplus

@@ -92,6 +92,7 @@ SIGNATURES = [
     ("lbm_batch_poll", _I, [_P, ctypes.POINTER(_P), _I, _IP]),
     ("lbm_batch_stats", _I, [_P, _IP, ctypes.POINTER(ctypes.c_size_t), _DP]),
     ("lbm_batch_set_tiles", _I, [_P, _I, _I, _I, _I, _I]),
+    ("lbm_batch_set_spin_limit", _I, [_P, ctypes.c_uint]),
     ("lbm_batch_destroy", _I, [_P]),
 ]
 

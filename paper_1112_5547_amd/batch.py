@@ -32,10 +32,13 @@ class Batch:
         self._members: Dict[int, Lattice] = {}
 
     def close(self):
-        if self._b:
-            check(lib().lbm_batch_destroy(self._b), "batch_destroy")
-            self._b = ctypes.c_void_p()
+        """Releases the batch.  The native object is freed even when destroy
+        reports an error (an unread persistent-launch give-up), so the handle
+        is dropped before the status is checked."""
         self._members.clear()
+        if self._b:
+            b, self._b = self._b, ctypes.c_void_p()
+            check(lib().lbm_batch_destroy(b), "batch_destroy")
 
     def __del__(self):
         try:
@@ -75,6 +78,10 @@ class Batch:
 
     def set_tiles(self, tx9: int = 0, tx19: int = 0, ty19: int = 0, mb9: int = 0, mb19: int = 0):
         check(lib().lbm_batch_set_tiles(self._b, tx9, tx19, ty19, mb9, mb19), "batch_set_tiles")
+
+    def set_spin_limit(self, spins: int):
+        """Grid-barrier polls before a persistent launch gives up (0: default)."""
+        check(lib().lbm_batch_set_spin_limit(self._b, int(spins)), "batch_set_spin_limit")
 
     @property
     def members(self) -> List[Lattice]:

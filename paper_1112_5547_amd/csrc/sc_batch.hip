@@ -24,10 +24,12 @@ using namespace sc;
 
 namespace {
 
-// Clears the claim counters of a persistent launch (a kernel, so that the
-// clear may sit inside a captured graph).
+// Clears the barrier words and claim counters of a persistent launch (a
+// kernel, so that the clear may sit inside a captured graph).  The timeout
+// flag is left alone: it stays set until the host has seen it.
 __global__ void k_zero_u32(unsigned* p, int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (i != SYNC_TIMEOUT) p[i] = 0u;
 }
 
 struct BatchCfg {
@@ -60,6 +62,8 @@ struct Group {
     hipEvent_t staged = nullptr;  // last upload from the staging buffers
     hipGraphExec_t gexec = nullptr;
     int g_mode = -1, g_nwork = -1, g_k = -1, g_grid = -1;
+    unsigned g_spin = 0;
+    bool pers_used = false;       // a persistent launch may have set the timeout flag
 };
 
 }  // namespace
@@ -72,6 +76,7 @@ struct lbm_batch {
     std::vector<Member> members;
     int nt = 256, tx19 = 64, ty19 = 4;
     int mb9 = 0, mb19 = 0;  // 0: each member's own march chunk
+    unsigned spin_limit = kSpinLimit;  // grid-barrier polls before a persistent launch gives up
     Group grp[kPolicies];   // one per kernel policy (precision, forcing, relaxation)
     int err = 0;
 };
@@ -135,9 +140,40 @@ int ensure(lbm_batch* b, Group& g, size_t ndesc, size_t nwork, int ksteps) {
         (void)hipFree(g.d_sync);
         g.d_sync = nullptr;
         BCALL(b, hipMalloc(&g.d_sync, cap * sizeof(unsigned)));
+        // a fresh timeout flag (the per-launch clear keeps it); enqueued
+        // before any capture begins
+        BCALL(b, hipMemsetAsync(g.d_sync, 0, cap * sizeof(unsigned), b->stream));
         g.sync_cap = cap;
         if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
         g.gexec = nullptr;
+    }
+    return LBM_OK;
+}
+
+// Waits for the batch's stream and reads the (sticky) timeout flag of every
+// group that ran a persistent launch.  A give-up leaves the members half
+// advanced: the batch and every member handle then report LBM_ETIMEOUT (the
+// handles accept only destroy).  Returns LBM_OK, LBM_ETIMEOUT or LBM_EDEVICE.
+int check_timeout(lbm_batch* b) {
+    if (hipStreamSynchronize(b->stream) != hipSuccess) {
+        b->err = LBM_EDEVICE;
+        return LBM_EDEVICE;
+    }
+    bool hit = false;
+    for (Group& g : b->grp) {
+        if (!g.d_sync || !g.pers_used) continue;
+        unsigned flag = 0;
+        if (hipMemcpy(&flag, g.d_sync + SYNC_TIMEOUT, sizeof(unsigned), hipMemcpyDeviceToHost) !=
+            hipSuccess) {
+            b->err = LBM_EDEVICE;
+            return LBM_EDEVICE;
+        }
+        hit = hit || flag != 0;
+    }
+    if (hit) {
+        b->err = LBM_ETIMEOUT;
+        for (Member& m : b->members) m.h->err = LBM_ETIMEOUT;
+        return LBM_ETIMEOUT;
     }
     return LBM_OK;
 }
@@ -147,17 +183,18 @@ int member_mb(const lbm_batch* b, const lbm_sc* h) {
     return o > 0 ? o : h->mb;
 }
 
-// Enqueues one epoch of the members of one kernel policy group.
-int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vector<int>& ksteps,
-              int K, int mode) {
-    Group& g = b->grp[pol];
-    // descriptors and the work list (largest-cost lattices first)
+// Descriptors and work list of one kernel policy group for an epoch: one
+// descriptor per member (both buffer parities, its tile and march chunk in
+// the batch's block shape) and its (member, tile, chunk) work items, the
+// largest-cost items first.
+void build_tables(lbm_batch* b, const std::vector<int>& idx, const std::vector<int>& ksteps,
+                  std::vector<BatchDesc>& descs, std::vector<WorkItem>& works) {
     struct Item {
         WorkItem w;
         double cost;
     };
     std::vector<Item> items;
-    std::vector<BatchDesc> descs(idx.size());
+    descs.assign(idx.size(), BatchDesc{});
     for (size_t m = 0; m < idx.size(); ++m) {
         lbm_sc* h = b->members[idx[m]].h;
         const int save_tx = h->tx, save_ty = h->ty, save_mb = h->mb;
@@ -186,11 +223,22 @@ int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vec
     }
     std::stable_sort(items.begin(), items.end(),
                      [](const Item& a, const Item& c) { return a.cost > c.cost; });
+    works.resize(items.size());
+    for (size_t i = 0; i < items.size(); ++i) works[i] = items[i].w;
+}
+
+// Enqueues one epoch of the members of one kernel policy group.
+int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vector<int>& ksteps,
+              int K, int mode) {
+    Group& g = b->grp[pol];
+    std::vector<BatchDesc> descs;
+    std::vector<WorkItem> items;
+    build_tables(b, idx, ksteps, descs, items);
     const int nwork = (int)items.size();
     int rc = ensure(b, g, descs.size(), items.size(), K);
     if (rc) return rc;
     memcpy(g.h_desc, descs.data(), descs.size() * sizeof(BatchDesc));
-    for (int i = 0; i < nwork; ++i) g.h_work[i] = items[i].w;
+    memcpy(g.h_work, items.data(), (size_t)nwork * sizeof(WorkItem));
     BCALL(b, hipMemcpyAsync(g.d_desc, g.h_desc, descs.size() * sizeof(BatchDesc),
                             hipMemcpyHostToDevice, b->stream));
     BCALL(b, hipMemcpyAsync(g.d_work, g.h_work, (size_t)nwork * sizeof(WorkItem),
@@ -214,7 +262,8 @@ int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vec
     }
     // replay the cached graph when the launch shape is unchanged (the tables
     // are rewritten in place, so the captured arguments stay valid)
-    if (!(g.gexec && g.g_mode == mode && g.g_nwork == nwork && g.g_k == K && g.g_grid == grid)) {
+    if (!(g.gexec && g.g_mode == mode && g.g_nwork == nwork && g.g_k == K && g.g_grid == grid &&
+          g.g_spin == b->spin_limit)) {
         if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
         g.gexec = nullptr;
         hipGraph_t graph = nullptr;
@@ -231,7 +280,7 @@ int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vec
             le = hipGetLastError();
             if (le == hipSuccess) {
                 hipLaunchKernelGGL(pf, dim3(grid), dim3(b->nt), 0, b->stream, g.d_desc, g.d_work,
-                                   nwork, K, g.d_sync);
+                                   nwork, K, g.d_sync, b->spin_limit);
                 le = hipGetLastError();
             }
         }
@@ -252,7 +301,9 @@ int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vec
         g.g_nwork = nwork;
         g.g_k = K;
         g.g_grid = grid;
+        g.g_spin = b->spin_limit;
     }
+    if (mode == LBM_BATCH_PERSISTENT) g.pers_used = true;
     BCALL(b, hipGraphLaunch(g.gexec, b->stream));
     return LBM_OK;
 }
@@ -305,11 +356,11 @@ int lbm_batch_remove(lbm_batch* b, lbm_sc* h) {
     for (size_t i = 0; i < b->members.size(); ++i)
         if (b->members[i].h == h) {
             (void)hipSetDevice(b->device);
-            (void)hipStreamSynchronize(b->stream);
+            const int rc = b->err ? b->err : check_timeout(b);
             h->batch = nullptr;
             b->used -= h->mem_bytes;
             b->members.erase(b->members.begin() + i);
-            return LBM_OK;
+            return rc;
         }
     return LBM_EINVAL;
 }
@@ -335,7 +386,7 @@ int lbm_batch_run(lbm_batch* b, int epoch_steps, int mode) {
             for (size_t m = 0; m < idx[pol].size(); ++m) {
                 lbm_sc* h = b->members[idx[pol][m]].h;
                 lbm_batch* keep = h->batch;
-                const int rc = sc_enqueue_steps(h, ks[pol][m], b->stream);
+                const int rc = sc_enqueue_steps(h, ks[pol][m], b->stream, false);
                 h->batch = keep;
                 if (rc) {
                     b->err = rc;
@@ -366,19 +417,8 @@ int lbm_batch_poll(lbm_batch* b, lbm_sc** done, int max_done, int* n_done) {
     *n_done = 0;
     if (b->err) return b->err;
     (void)hipSetDevice(b->device);
-    BCALL(b, hipStreamSynchronize(b->stream));
-    for (int pol = 0; pol < kPolicies; ++pol) {
-        Group& g = b->grp[pol];
-        if (g.d_sync && g.g_mode == LBM_BATCH_PERSISTENT) {
-            unsigned flag = 0;
-            BCALL(b, hipMemcpy(&flag, g.d_sync + SYNC_TIMEOUT, sizeof(unsigned),
-                               hipMemcpyDeviceToHost));
-            if (flag) {
-                b->err = LBM_ETIMEOUT;
-                return LBM_ETIMEOUT;
-            }
-        }
-    }
+    const int rc = check_timeout(b);
+    if (rc) return rc;
     for (const Member& m : b->members)
         if (m.remaining <= 0 && *n_done < max_done) done[(*n_done)++] = m.h;
     return LBM_OK;
@@ -416,15 +456,21 @@ int lbm_batch_set_tiles(lbm_batch* b, int tx9, int tx19, int ty19, int mb9, int 
     return LBM_OK;
 }
 
+int lbm_batch_set_spin_limit(lbm_batch* b, unsigned spins) {
+    if (!b) return LBM_EINVAL;
+    b->spin_limit = spins ? spins : kSpinLimit;
+    return LBM_OK;
+}
+
 int lbm_batch_destroy(lbm_batch* b) {
     if (!b) return LBM_OK;
     (void)hipSetDevice(b->device);
-    (void)hipStreamSynchronize(b->stream);
+    const int rc = b->err ? b->err : check_timeout(b);
     for (Member& m : b->members) m.h->batch = nullptr;
     for (Group& g : b->grp) free_group(g);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
-    return LBM_OK;
+    return rc == LBM_ETIMEOUT ? rc : LBM_OK;
 }
 
 }  // extern "C"

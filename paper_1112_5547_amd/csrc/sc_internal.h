@@ -60,12 +60,14 @@ struct WorkItem {
 };
 
 // sync words: [0] barrier count, [1] barrier generation, [2] timeout flag,
-// [3..3+K) per-step tile claim counters
+// [3..3+K) per-step tile claim counters.  The timeout flag is sticky: the
+// per-launch clear leaves it alone, so a give-up stays visible until the
+// host has read it.
 constexpr int SYNC_COUNT = 0, SYNC_GEN = 1, SYNC_TIMEOUT = 2, SYNC_CTR = 3;
 constexpr unsigned kSpinLimit = 1u << 26;  // ~seconds of s_sleep polling per barrier
 
 using BatchStepFn = void (*)(const BatchDesc*, const WorkItem*, int, int);
-using BatchPersFn = void (*)(const BatchDesc*, const WorkItem*, int, int, unsigned*);
+using BatchPersFn = void (*)(const BatchDesc*, const WorkItem*, int, int, unsigned*, unsigned);
 
 // single-lattice step of policy pol (variant 0 fused, 1 two-pass, 2 pipelined,
 // 3 re-pull); batch kernels of policy pol for a block shape

@@ -194,9 +194,10 @@ hipError_t launch_set_plane(int Q, int prec, void* f, uint32_t NS, const double*
 //   pass 1: rho_s(x) = sum_i f_is(x, t)      (FP64, shifted: rho_ref + sum h)
 //   pass 2: j_s, force F_s = -G rho_s sum_i w_i rho_s'(x + c_i) c_i (+ body),
 //           u_phys = (j_A + j_B + F/2) / rho, bulk pressure, probe means,
-//           phi >= 0 count, non-finite count; per-block partials reduced in a
-//           fixed LDS tree order
-//   pass 3: one block reduces the partials in a fixed order.
+//           phi >= 0 count, non-finite count; per-block partials: a fixed
+//           cross-lane butterfly within each wave, then one LDS step over the
+//           block's waves
+//   pass 3: one block reduces the partials the same way.
 // ---------------------------------------------------------------------------
 template <int Q, class PR>
 __global__ void __launch_bounds__(256) k_rho64(const typename PR::T* f, double* rho, int nx, int ny,
@@ -219,10 +220,45 @@ __global__ void __launch_bounds__(256) k_rho64(const typename PR::T* f, double* 
 
 __device__ __forceinline__ bool is_max_slot(int k) { return k == T_MAX_U; }
 
+// Reduction of one total over the 64 lanes of a wave: a butterfly over lane
+// distances 32, 16, ..., 1 (cross-lane permutes, no LDS traffic, no barrier).
+// The order of the operations is fixed, so the result is the same on every
+// run; lane 0's value is the one used.
+__device__ __forceinline__ double wave_reduce(double v, bool is_max) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const double o = __shfl_xor(v, m, 64);
+        v = is_max ? fmax(v, o) : v + o;
+    }
+    return v;
+}
+
+// Block reduction of the T_COUNT totals: each wave reduces its lanes, then
+// one LDS step combines the waves in wave order.  Thread k < T_COUNT returns
+// total k.
+template <int NT>
+__device__ __forceinline__ double block_reduce(double (&v)[T_COUNT], double (&red)[T_COUNT][NT / 64]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < T_COUNT; ++k) {
+        const double r = wave_reduce(v[k], is_max_slot(k));
+        if (lane == 0) red[k][wave] = r;
+    }
+    __syncthreads();
+    double out = 0.0;
+    if ((int)threadIdx.x < T_COUNT) {
+        const int k = threadIdx.x;
+        out = red[k][0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) out = is_max_slot(k) ? fmax(out, red[k][w]) : out + red[k][w];
+    }
+    return out;
+}
+
 template <int Q, class PR>
 __global__ void __launch_bounds__(OBS_BLOCK) k_observe(ObsArgs a) {
     using T = typename PR::T;
-    __shared__ double red[T_COUNT][OBS_BLOCK];
+    __shared__ double red[T_COUNT][OBS_BLOCK / 64];
     const uint32_t site = blockIdx.x * (uint32_t)OBS_BLOCK + threadIdx.x;
     double v[T_COUNT];
 #pragma unroll
@@ -302,25 +338,12 @@ __global__ void __launch_bounds__(OBS_BLOCK) k_observe(ObsArgs a) {
             }
         }
     }
-#pragma unroll
-    for (int k = 0; k < T_COUNT; ++k) red[k][threadIdx.x] = v[k];
-    __syncthreads();
-    for (int stride = OBS_BLOCK / 2; stride > 0; stride >>= 1) {
-        if ((int)threadIdx.x < stride) {
-#pragma unroll
-            for (int k = 0; k < T_COUNT; ++k) {
-                const double o = red[k][threadIdx.x + stride];
-                red[k][threadIdx.x] = is_max_slot(k) ? fmax(red[k][threadIdx.x], o)
-                                                     : red[k][threadIdx.x] + o;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < T_COUNT) a.partial[(size_t)blockIdx.x * T_COUNT + threadIdx.x] = red[threadIdx.x][0];
+    const double tot = block_reduce<OBS_BLOCK>(v, red);
+    if (threadIdx.x < T_COUNT) a.partial[(size_t)blockIdx.x * T_COUNT + threadIdx.x] = tot;
 }
 
 __global__ void __launch_bounds__(256) k_finalize(const double* partial, int nparts, double* out) {
-    __shared__ double red[T_COUNT][256];
+    __shared__ double red[T_COUNT][256 / 64];
     double v[T_COUNT];
 #pragma unroll
     for (int k = 0; k < T_COUNT; ++k) v[k] = 0.0;
@@ -331,21 +354,8 @@ __global__ void __launch_bounds__(256) k_finalize(const double* partial, int npa
             v[k] = is_max_slot(k) ? fmax(v[k], o) : v[k] + o;
         }
     }
-#pragma unroll
-    for (int k = 0; k < T_COUNT; ++k) red[k][threadIdx.x] = v[k];
-    __syncthreads();
-    for (int stride = 128; stride > 0; stride >>= 1) {
-        if ((int)threadIdx.x < stride) {
-#pragma unroll
-            for (int k = 0; k < T_COUNT; ++k) {
-                const double o = red[k][threadIdx.x + stride];
-                red[k][threadIdx.x] = is_max_slot(k) ? fmax(red[k][threadIdx.x], o)
-                                                     : red[k][threadIdx.x] + o;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < T_COUNT) out[threadIdx.x] = red[threadIdx.x][0];
+    const double tot = block_reduce<256>(v, red);
+    if (threadIdx.x < T_COUNT) out[threadIdx.x] = tot;
 }
 
 int observe_blocks(uint32_t N) { return (int)((N + OBS_BLOCK - 1) / OBS_BLOCK); }

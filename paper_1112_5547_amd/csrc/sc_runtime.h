@@ -63,4 +63,8 @@ uint32_t sc_array_stride(const lbm_sc_params* p);
 void sc_default_kernel(const lbm_sc_params* p, int* variant, int* tx, int* ty, int* mb);
 sc::StepParams sc_step_params(const lbm_sc* h, int parity);
 hipError_t sc_launch_step(lbm_sc* h, int parity, hipStream_t s);
-int sc_enqueue_steps(lbm_sc* h, long long n, hipStream_t s);
+// Enqueues n steps on stream s.  allow_graph: replay captured 32-step graphs
+// when s is the handle's own stream and the lattice is small enough for
+// launches to dominate (the per-lattice batch baseline passes false: one
+// launch per lattice per step, whichever stream it shares).
+int sc_enqueue_steps(lbm_sc* h, long long n, hipStream_t s, bool allow_graph = true);

@@ -239,9 +239,9 @@ int capture_graph(lbm_sc* h, int parity) {
 
 }  // namespace
 
-int sc_enqueue_steps(lbm_sc* h, long long n, hipStream_t s) {
+int sc_enqueue_steps(lbm_sc* h, long long n, hipStream_t s, bool allow_graph) {
     if (n <= 0) return LBM_OK;
-    if (s == h->stream && n >= kGraphSteps && wants_graph(h)) {
+    if (allow_graph && s == h->stream && n >= kGraphSteps && wants_graph(h)) {
         while (n >= kGraphSteps) {
             if (!h->gexec[h->cur]) {
                 int rc = capture_graph(h, h->cur);

@@ -290,7 +290,8 @@ __device__ __forceinline__ unsigned ld_acquire(unsigned* p) {
 // Grid-wide barrier for co-resident blocks; returns false if the wait hit
 // the spin limit or another block already reported a timeout (all blocks
 // then leave the kernel, so every wave terminates).
-__device__ inline bool grid_barrier(unsigned* sync, unsigned nblocks, unsigned& gen, int* s_flag) {
+__device__ inline bool grid_barrier(unsigned* sync, unsigned nblocks, unsigned& gen, int* s_flag,
+                                    unsigned spin_limit) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -304,7 +305,7 @@ __device__ inline bool grid_barrier(unsigned* sync, unsigned nblocks, unsigned& 
         } else {
             unsigned spins = 0;
             while (ld_acquire(&sync[SYNC_GEN]) == g) {
-                if (ld_acquire(&sync[SYNC_TIMEOUT]) != 0u || ++spins > kSpinLimit) {
+                if (ld_acquire(&sync[SYNC_TIMEOUT]) != 0u || ++spins > spin_limit) {
                     __hip_atomic_store(&sync[SYNC_TIMEOUT], 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     ok = 0;
@@ -325,7 +326,7 @@ __device__ inline bool grid_barrier(unsigned* sync, unsigned nblocks, unsigned& 
 template <class PR, int NT, int TX19, int TY19>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<PR>::value)))
 k_batch_persistent(const BatchDesc* __restrict__ desc, const WorkItem* __restrict__ work,
-                   int nwork, int ksteps, unsigned* sync) {
+                   int nwork, int ksteps, unsigned* sync, unsigned spin_limit) {
     using BT = BatchTiles<PR, NT, TX19, TY19>;
     __shared__ typename PR::A lds[BT::LDS_ELEMS];
     __shared__ int s_item;
@@ -344,7 +345,7 @@ k_batch_persistent(const BatchDesc* __restrict__ desc, const WorkItem* __restric
             const BatchDesc& d = desc[w.member];
             if (k < d.steps) BT::run(d, w, k, lds);
         }
-        if (k + 1 < ksteps && !grid_barrier(sync, gridDim.x, gen, &s_flag)) return;
+        if (k + 1 < ksteps && !grid_barrier(sync, gridDim.x, gen, &s_flag, spin_limit)) return;
     }
 }
 

@@ -81,8 +81,11 @@ class Lattice:
     # -- lifetime --------------------------------------------------------
     def close(self):
         if self._h:
-            check(lib().lbm_sc_destroy(self._h), "destroy")
-            self._h = ctypes.c_void_p()
+            h, self._h = self._h, ctypes.c_void_p()
+            rc = lib().lbm_sc_destroy(h)
+            if rc == _abi.LBM_ESTATE:      # still in a batch: nothing was freed
+                self._h = h
+            check(rc, "destroy")
         self._arena = None
         self._stream = None
 
