@@ -1,15 +1,34 @@
-"""Batched launches give each lattice bitwise the result it has alone.
+"""Batched launches against the oracle, and alone against in the mix.
 
-Every batch mode runs the same per-site device code as a single-lattice
-launch, so the alone-vs-in-the-mix comparison is exact equality, for FP64
-and FP32-shifted members, D2Q9 and D3Q19 in one launch, uneven sizes,
-members with different step counts and members joining mid-run.
+Every batched member is compared with the FP64 CPU oracle run from the same
+seeded fields (Sec. 2.1 step by step): populations within 1e-12 in FP64 and
+2e-6 in FP32 shifted storage.  Every batch mode also runs the same per-site
+device code as a single-lattice launch, so the alone-vs-in-the-mix comparison
+is exact equality, for FP64 and FP32-shifted members, D2Q9 and D3Q19 in one
+launch, uneven sizes, members with different step counts, members joining
+mid-run, and every compiled batch block shape with and without march-chunk
+overrides.
 """
 import numpy as np
 import pytest
 
+import oracle
 import sc_inputs
-from gpu_common import say
+from gpu_common import maxabs, say
+
+TOL = {"fp64": 1e-12, "fp32_shifted": 2e-6}
+_ORACLE = {}
+
+
+def _oracle(spec, seed):
+    """Oracle populations of a member after its steps (cached per spec, seed)."""
+    key = (spec, seed)
+    if key not in _ORACLE:
+        q, nx, ny, nz, tau, G, steps, kind = spec
+        fl = _fields(q, nx, ny, nz, kind, seed)
+        _ORACLE[key] = oracle.run(oracle.init(q, fl.rho_A, fl.rho_B), tau, tau, G, steps,
+                                  all_cores=True)
+    return _ORACLE[key]
 
 pytestmark = pytest.mark.gpu
 
@@ -62,10 +81,45 @@ def test_batch_equals_solo_bitwise(mode, precision):
         if len(done) == len(lats):
             break
     assert len(done) == len(lats)
-    for lat, spec, ref in zip(lats, SPECS, solo):
+    for k, (lat, spec, ref) in enumerate(zip(lats, SPECS, solo)):
         assert lat.steps_done == spec[6]
         b.remove(lat)
-        assert np.array_equal(lat.get_populations(), ref), spec
+        f = lat.get_populations()
+        assert np.array_equal(f, ref), spec
+        err = maxabs(f, _oracle(spec, 100 + k))
+        assert err <= TOL[precision], (spec, err)
+    b.close()
+
+
+# every block shape the batch kernels are compiled for (tx9 = block size,
+# tx19 x ty19 the D3Q19 tile), each with its default march chunks and with
+# overridden ones
+BATCH_CFGS = [(256, 64, 4), (256, 32, 8), (256, 16, 16), (128, 32, 4), (512, 64, 8),
+              (512, 32, 16)]
+
+
+@pytest.mark.parametrize("cfg", BATCH_CFGS)
+@pytest.mark.parametrize("mbs", [(0, 0), (5, 3)])
+@pytest.mark.parametrize("mode", ["fused", "persistent"])
+def test_every_batch_block_shape_against_oracle(cfg, mbs, mode):
+    from paper_1112_5547_amd import Batch
+    precision = "fp32_shifted" if cfg[0] != 512 else "fp64"
+    say(f"batch tiles {cfg} mb {mbs} mode={mode} {precision}")
+    b = Batch()
+    b.set_tiles(cfg[0], cfg[1], cfg[2], mbs[0], mbs[1])
+    lats = [_make(spec, 100 + k, precision) for k, spec in enumerate(SPECS)]
+    for lat, spec in zip(lats, SPECS):
+        assert b.add(lat, spec[6])
+    for _ in range(10):
+        b.run(16, mode)
+        if len(b.poll()) == len(lats):
+            break
+    for k, (lat, spec) in enumerate(zip(lats, SPECS)):
+        assert lat.steps_done == spec[6]
+        b.remove(lat)
+        err = maxabs(lat.get_populations(), _oracle(spec, 100 + k))
+        assert err <= TOL[precision], (spec, err)
+        lat.close()
     b.close()
 
 
@@ -111,3 +165,41 @@ def test_member_cannot_step_alone_while_batched():
     b.remove(lat)
     lat.step(1)
     b.close()
+
+
+def test_persistent_barrier_give_up_is_reported():
+    """A spin limit of one poll makes the first block that waits at a grid
+    barrier give up: every block leaves the kernel (the give-up flag is
+    checked at every poll), poll reports LBM_ETIMEOUT, the members are failed
+    and only removal and destroy are accepted; a new batch then runs normally."""
+    from paper_1112_5547_amd import Batch, LbmError
+    from paper_1112_5547_amd._abi import LBM_ETIMEOUT
+    say("persistent batch with a one-poll barrier spin limit")
+    b = Batch()
+    b.set_spin_limit(1)
+    lats = [_make(spec, 100 + k, "fp32_shifted") for k, spec in enumerate(SPECS)]
+    for lat, spec in zip(lats, SPECS):
+        assert b.add(lat, spec[6])
+    b.run(16, "persistent")
+    with pytest.raises(LbmError) as e:
+        b.poll()
+    assert e.value.status == LBM_ETIMEOUT
+    with pytest.raises(LbmError) as e:
+        lats[0].step(1)
+    assert e.value.status == LBM_ETIMEOUT
+    for lat in lats:
+        with pytest.raises(LbmError) as e:
+            b.remove(lat)
+        assert e.value.status == LBM_ETIMEOUT
+        lat.close()
+    with pytest.raises(LbmError):
+        b.close()
+    say("fresh persistent batch after the give-up")
+    b2 = Batch()
+    lat = _make(SPECS[0], 100, "fp32_shifted")
+    b2.add(lat, SPECS[0][6])
+    while not b2.poll():
+        b2.run(16, "persistent")
+    b2.remove(lat)
+    assert maxabs(lat.get_populations(), _oracle(SPECS[0], 100)) <= TOL["fp32_shifted"]
+    b2.close()

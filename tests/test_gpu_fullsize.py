@@ -35,18 +35,26 @@ def _sample_sites(n, k, seed):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_shifted", 2e-6)])
-def test_256cube_one_step_sampled(spinodal256, precision, tol):
-    from paper_1112_5547_amd import Lattice
+@pytest.mark.parametrize("forcing,tau_minus", [("shift", None), ("guo", None),
+                                               ("shift", (0.8, 0.8))])
+def test_256cube_one_step_sampled(spinodal256, precision, tol, forcing, tau_minus):
+    """The benchmark's step kernels (the tuned configuration bench.py times,
+    for the velocity shift, Guo forcing and two relaxation times) against the
+    oracle's one-site-at-a-time step."""
+    from paper_1112_5547_amd import Lattice, autotune
     fl = spinodal256
-    say(f"256^3 D3Q19 {precision}: init + 1 step (benchmark kernel config)")
-    lat = Lattice(19, L, L, L, tau_A=TAU, G=G, precision=precision)
+    say(f"256^3 D3Q19 {precision} {forcing} tau- {tau_minus}: init + 1 step (bench kernel)")
+    lat = Lattice(19, L, L, L, tau_A=TAU, G=G, precision=precision, forcing=forcing,
+                  tau_minus=tau_minus)
+    autotune.apply(lat)
+    say(f"kernel {lat.kernel}")
     lat.init(fl.rho_A, fl.rho_B)
     lat.step(1)
     f = lat.get_populations().reshape(2, 19, -1)
     lat.close()
     f0 = oracle.init(19, fl.rho_A, fl.rho_B)
     sites = _sample_sites(L ** 3, 3000, 1)
-    want = oracle.step_sites(f0, TAU, TAU, G, sites)
+    want = oracle.step_sites(f0, TAU, TAU, G, sites, forcing=forcing, tau_minus=tau_minus)
     got = f[:, :, sites].transpose(2, 0, 1)
     assert float(np.abs(got - want).max()) <= tol
 

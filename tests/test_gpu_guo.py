@@ -40,7 +40,8 @@ def test_guo_fp32_shifted_within_fp32_bounds():
 def test_guo_variants_agree_bitwise(precision):
     fl = sc_inputs.drop(40, 36, 30, radius=8, seed=3)
     ref = None
-    for k in [(0, 64, 4, 8), (0, 32, 8, 3), (1, 64, 4, 4), (2, 64, 4, 8), (3, 32, 16, 6)]:
+    for k in [(0, 64, 4, 8), (0, 32, 8, 3), (1, 64, 4, 4), (2, 64, 4, 8), (3, 32, 16, 6),
+              (0, 64, 8, 7), (2, 64, 8, 5)]:
         say(f"guo variants {precision} kernel {k}")
         lat, f = gpu_run(19, fl.rho_A, fl.rho_B, 0.9, 1.1, 1.4, 30, precision=precision,
                          kernel=k, body_A=2e-6, forcing="guo")
@@ -49,6 +50,8 @@ def test_guo_variants_agree_bitwise(precision):
             ref = f
         else:
             assert np.array_equal(f, ref), k
+    ref_o = oracle_run(19, fl.rho_A, fl.rho_B, 0.9, 1.1, 1.4, 30, body_A=2e-6, forcing="guo")
+    assert maxabs(ref, ref_o) <= (1e-12 if precision == "fp64" else 2e-6)
 
 
 @pytest.mark.parametrize("mode", ["fused", "persistent"])

@@ -45,7 +45,8 @@ def test_trt_fp32_shifted_within_fp32_bounds():
 def test_trt_variants_agree_bitwise(precision, forcing):
     fl = sc_inputs.drop(40, 36, 30, radius=8, seed=3)
     ref = None
-    for k in [(0, 64, 4, 8), (0, 32, 8, 3), (1, 64, 4, 4), (2, 64, 4, 8), (3, 32, 16, 6)]:
+    for k in [(0, 64, 4, 8), (0, 32, 8, 3), (1, 64, 4, 4), (2, 64, 4, 8), (3, 32, 16, 6),
+              (0, 64, 8, 7), (2, 64, 8, 5)]:
         say(f"trt variants {precision} {forcing} kernel {k}")
         lat, f = gpu_run(19, fl.rho_A, fl.rho_B, 0.9, 1.1, 1.4, 30, precision=precision,
                          kernel=k, forcing=forcing, tau_minus=TM)
@@ -54,6 +55,9 @@ def test_trt_variants_agree_bitwise(precision, forcing):
             ref = f
         else:
             assert np.array_equal(f, ref), k
+    ref_o = oracle_run(19, fl.rho_A, fl.rho_B, 0.9, 1.1, 1.4, 30, forcing=forcing,
+                       tau_minus=TM)
+    assert maxabs(ref, ref_o) <= (1e-12 if precision == "fp64" else 2e-6)
 
 
 def test_batch_mixing_bgk_and_trt_equals_solo():
