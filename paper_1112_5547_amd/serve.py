@@ -23,7 +23,13 @@ counts) arrive over time.  The loop:
       ``aging`` > 0 the order key is the remaining work in seconds (at
       ``nominal_rate`` site updates per second) minus ``aging`` times the time
       the job has spent in the system, so that a large job cannot be passed
-      over indefinitely by a stream of smaller ones;
+      over indefinitely by a stream of smaller ones.  With ``guard`` set,
+      every job also carries the completion time it would have under
+      one-job-at-a-time service in arrival order (at ``nominal_rate``); a
+      resident job whose slack against that deadline (deadline - now -
+      remaining work) falls to ``guard`` seconds or less is served first,
+      earliest deadline first, so that no job finishes much later than it
+      would have in arrival order while the others keep the SRPT order;
     - ``"all"``: every resident job advances every epoch (each job gets the
       same number of steps per epoch, whatever its size);
 * while an epoch runs on the device, prepares the next admissions on the host
@@ -156,7 +162,8 @@ class Server:
                  keep_populations: bool = False, admit_hook: Optional[Callable] = None,
                  tiles: Optional[dict] = None, policy: str = "srpt",
                  sat_sites: int = 4_000_000, aging: float = 0.0,
-                 nominal_rate: float = 1e10, solo_alone: bool = True):
+                 nominal_rate: float = 1e10, solo_alone: bool = True,
+                 guard: Optional[float] = None):
         if policy not in ("srpt", "all"):
             raise ValueError(f"unknown scheduling policy {policy!r}")
         self.policy = policy
@@ -164,6 +171,7 @@ class Server:
         self.aging = float(aging)
         self.solo_alone = bool(solo_alone)
         self.nominal_rate = float(nominal_rate)
+        self.guard = None if guard is None else float(guard)
         self.budget = int(hbm_budget)
         self.epoch_steps = int(epoch_steps)
         self.mode = mode
@@ -194,6 +202,13 @@ class Server:
                             self.tiles["mb9"], self.tiles["mb19"])
         epochs = 0
         need = {j.job_id: be.bytes_needed(j) for j in pending}
+        # completion time of each job under one-job-at-a-time service in
+        # arrival order at the nominal rate (depends on earlier arrivals only)
+        deadline: Dict[int, float] = {}
+        v = 0.0
+        for j in pending:
+            v = max(v, j.arrival) + j.sites * j.steps / self.nominal_rate
+            deadline[j.job_id] = v
 
         def admit():
             nonlocal used, refused
@@ -244,6 +259,14 @@ class Server:
                 return (work_s - self.aging * (now - job.arrival), job.arrival, j)
 
             order = sorted(resident, key=key)
+            if self.guard is not None:
+                def slack(j):
+                    job = resident[j][0]
+                    return deadline[j] - now - remaining(j) * job.sites / self.nominal_rate
+                urgent = sorted((j for j in order if slack(j) <= self.guard),
+                                key=lambda j: (deadline[j], j))
+                late = set(urgent)
+                order = urgent + [j for j in order if j not in late]
             chosen, sites = [], 0
             for jid in order:
                 n = resident[jid][0].sites
