@@ -88,7 +88,8 @@ enum {
     LBM_ESTATE = -4,      /* call out of order (e.g. step before init) */
     LBM_ENONFINITE = -5,  /* a reduced total is NaN or Inf */
     LBM_EBUDGET = -6,     /* a batch has no room for the lattice */
-    LBM_ETIMEOUT = -7     /* a persistent launch hit its grid-barrier spin limit */
+    LBM_ETIMEOUT = -7,    /* a persistent launch hit its grid-barrier spin limit */
+    LBM_ETOOBIG = -8      /* beyond the allocation-free batch run's fixed scratch */
 };
 
 /* Lattice parameters.  Validation (LBM_EINVAL otherwise):
@@ -277,6 +278,25 @@ int lbm_batch_remove(lbm_batch *b, lbm_sc *h);
 /* Enqueues up to epoch_steps steps of every member with steps remaining.
  * Asynchronous; graph-captured where the mode allows. */
 int lbm_batch_run(lbm_batch *b, int epoch_steps, int mode);
+
+/* Allocation-free variant of lbm_batch_run, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  No device memory is allocated and no graph is
+ * built: the fused form's descriptor table and work list are copied into a
+ * fixed device array of the library (about 4.5 MB, one per GPU, held until
+ * the process ends) and the epoch is launched directly, one kernel per step.
+ * Limits per kernel policy group (precision x forcing x relaxation):
+ * 1024 members and 262144 work items (tiles x march chunks); beyond them the
+ * call returns LBM_ETOOBIG before enqueueing anything.
+ * mode: LBM_BATCH_FUSED, or LBM_BATCH_PER_LATTICE (which uses no tables and
+ * runs as lbm_batch_run does); LBM_BATCH_PERSISTENT returns LBM_EINVAL.
+ * Results are bitwise those of lbm_batch_run (the same kernels).
+ * Every call on a GPU shares that GPU's array and overwrites it: calls that
+ * overlap on one GPU (from several batches or threads, on different
+ * streams) race and must be serialised by the caller.  The host-side tables
+ * are staged in memory the batch keeps; each call waits for the previous
+ * upload of its batch before reusing it. */
+int lbm_batch_run_noalloc(lbm_batch *b, int epoch_steps, int mode);
 
 /* Waits for the batch's stream, then writes up to max_done members whose
  * steps are complete into done[] and their count into *n_done (finished

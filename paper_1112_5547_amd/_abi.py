@@ -18,6 +18,7 @@ LBM_FP64, LBM_FP32_SHIFTED = 0, 1
 LBM_FORCING_SHIFT, LBM_FORCING_GUO = 0, 1
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE = 0, -1, -2, -3
 LBM_ESTATE, LBM_ENONFINITE, LBM_EBUDGET, LBM_ETIMEOUT = -4, -5, -6, -7
+LBM_ETOOBIG = -8
 LBM_BATCH_PER_LATTICE, LBM_BATCH_FUSED, LBM_BATCH_PERSISTENT = 0, 1, 2
 
 
@@ -89,6 +90,7 @@ SIGNATURES = [
     ("lbm_batch_add", _I, [_P, _P, ctypes.c_longlong]),
     ("lbm_batch_remove", _I, [_P, _P]),
     ("lbm_batch_run", _I, [_P, _I, _I]),
+    ("lbm_batch_run_noalloc", _I, [_P, _I, _I]),
     ("lbm_batch_poll", _I, [_P, ctypes.POINTER(_P), _I, _IP]),
     ("lbm_batch_stats", _I, [_P, _IP, ctypes.POINTER(ctypes.c_size_t), _DP]),
     ("lbm_batch_set_tiles", _I, [_P, _I, _I, _I, _I, _I]),

@@ -62,6 +62,13 @@ class Batch:
     def run(self, epoch_steps: int, mode: str = "persistent"):
         check(lib().lbm_batch_run(self._b, int(epoch_steps), MODES[mode]), "batch_run")
 
+    def run_noalloc(self, epoch_steps: int, mode: str = "fused"):
+        """The same epoch without device allocations: the fused form's tables go
+        to the library's fixed per-GPU scratch array (calls on one GPU must not
+        overlap)."""
+        check(lib().lbm_batch_run_noalloc(self._b, int(epoch_steps), MODES[mode]),
+              "batch_run_noalloc")
+
     def poll(self) -> List[Lattice]:
         """Waits for queued work; returns members whose steps are complete."""
         n = max(1, len(self._members))

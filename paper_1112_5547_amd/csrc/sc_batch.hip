@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -70,6 +71,8 @@ struct Group {
 
 struct lbm_batch {
     size_t budget = 0, used = 0;
+    std::vector<unsigned char> na_host;  // host staging of the allocation-free run
+    hipEvent_t na_staged = nullptr;      // its last upload
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
@@ -308,6 +311,43 @@ int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vec
     return LBM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free run (lbm_batch_run_noalloc).  The fused form's descriptor
+// table and work list go to a fixed device array instead of buffers the batch
+// allocates.  Every GPU the library runs on holds its own copy of the array
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the device (the array's name is a host-side
+// stand-in, not a device address).
+// ---------------------------------------------------------------------------
+constexpr int kNoAllocMaxMembers = 1024;   // members of one kernel policy group
+constexpr int kNoAllocMaxWork = 1 << 18;   // work items of one kernel policy group
+constexpr size_t kNoAllocDescBytes =
+    ((size_t)kNoAllocMaxMembers * sizeof(BatchDesc) + 255) / 256 * 256;
+constexpr size_t kNoAllocScratchBytes =
+    kNoAllocDescBytes + (size_t)kNoAllocMaxWork * sizeof(WorkItem);
+static_assert(kNoAllocScratchBytes <= (5u << 20), "scratch stays a few MB");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array, looked up once per device with
+// that device current (the caller has set it).
+int scratch_address(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return LBM_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return LBM_EDEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -330,6 +370,11 @@ int lbm_batch_create(lbm_batch** out, size_t hbm_budget, void* stream) {
             return LBM_EDEVICE;
         }
         b->own_stream = true;
+    }
+    if (hipEventCreateWithFlags(&b->na_staged, hipEventDisableTiming) != hipSuccess) {
+        if (b->own_stream) (void)hipStreamDestroy(b->stream);
+        delete b;
+        return LBM_EDEVICE;
     }
     *out = b;
     return LBM_OK;
@@ -412,6 +457,72 @@ int lbm_batch_run(lbm_batch* b, int epoch_steps, int mode) {
     return LBM_OK;
 }
 
+int lbm_batch_run_noalloc(lbm_batch* b, int epoch_steps, int mode) {
+    if (!b || epoch_steps < 0) return LBM_EINVAL;
+    if (b->err) return b->err;
+    if (mode == LBM_BATCH_PER_LATTICE) return lbm_batch_run(b, epoch_steps, mode);  // launches only
+    if (mode != LBM_BATCH_FUSED) return LBM_EINVAL;
+    if (epoch_steps == 0) return LBM_OK;
+    (void)hipSetDevice(b->device);
+    unsigned char* scr = nullptr;
+    int rc = scratch_address(b->device, &scr);
+    if (rc) return rc;
+    std::vector<int> idx[kPolicies], ks[kPolicies];
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        Member& m = b->members[i];
+        if (m.remaining <= 0 || m.h->err) continue;
+        const int k = (int)std::min<long long>(m.remaining, epoch_steps);
+        const int pol = sc_policy(m.h->p);
+        idx[pol].push_back((int)i);
+        ks[pol].push_back(k);
+    }
+    // every group's tables first: a batch beyond the scratch limits is
+    // refused before anything is enqueued
+    std::vector<BatchDesc> descs[kPolicies];
+    std::vector<WorkItem> works[kPolicies];
+    for (int pol = 0; pol < kPolicies; ++pol) {
+        if (idx[pol].empty()) continue;
+        build_tables(b, idx[pol], ks[pol], descs[pol], works[pol]);
+        if (descs[pol].size() > (size_t)kNoAllocMaxMembers ||
+            works[pol].size() > (size_t)kNoAllocMaxWork)
+            return LBM_ETOOBIG;
+    }
+    for (int pol = 0; pol < kPolicies; ++pol) {
+        if (idx[pol].empty()) continue;
+        BatchStepFn sf = nullptr;
+        BatchPersFn pf = nullptr;
+        if (!batch_kernels(pol, b->nt, b->tx19, b->ty19, &sf, &pf)) return LBM_EINVAL;
+        const size_t dbytes = descs[pol].size() * sizeof(BatchDesc);
+        const size_t wbytes = works[pol].size() * sizeof(WorkItem);
+        // the staging buffer may still feed the previous upload
+        BCALL(b, hipEventSynchronize(b->na_staged));
+        if (b->na_host.size() < kNoAllocScratchBytes) b->na_host.resize(kNoAllocScratchBytes);
+        memcpy(b->na_host.data(), descs[pol].data(), dbytes);
+        memcpy(b->na_host.data() + kNoAllocDescBytes, works[pol].data(), wbytes);
+        // one group's tables at a time: the upload of the next group is
+        // stream-ordered after this group's kernels
+        BCALL(b, hipMemcpyAsync(scr, b->na_host.data(), dbytes, hipMemcpyHostToDevice, b->stream));
+        BCALL(b, hipMemcpyAsync(scr + kNoAllocDescBytes, b->na_host.data() + kNoAllocDescBytes,
+                                wbytes, hipMemcpyHostToDevice, b->stream));
+        BCALL(b, hipEventRecord(b->na_staged, b->stream));
+        const BatchDesc* d_desc = reinterpret_cast<const BatchDesc*>(scr);
+        const WorkItem* d_work = reinterpret_cast<const WorkItem*>(scr + kNoAllocDescBytes);
+        const int nwork = (int)works[pol].size();
+        const int K = *std::max_element(ks[pol].begin(), ks[pol].end());
+        for (int k = 0; k < K; ++k) {
+            hipLaunchKernelGGL(sf, dim3(nwork), dim3(b->nt), 0, b->stream, d_desc, d_work, nwork, k);
+            BCALL(b, hipGetLastError());
+        }
+        for (size_t m = 0; m < idx[pol].size(); ++m) {
+            Member& mm = b->members[idx[pol][m]];
+            mm.h->cur ^= (ks[pol][m] & 1);
+            mm.h->steps += ks[pol][m];
+            mm.remaining -= ks[pol][m];
+        }
+    }
+    return LBM_OK;
+}
+
 int lbm_batch_poll(lbm_batch* b, lbm_sc** done, int max_done, int* n_done) {
     if (!b || !n_done || max_done < 0 || (max_done > 0 && !done)) return LBM_EINVAL;
     *n_done = 0;
@@ -468,6 +579,7 @@ int lbm_batch_destroy(lbm_batch* b) {
     const int rc = b->err ? b->err : check_timeout(b);
     for (Member& m : b->members) m.h->batch = nullptr;
     for (Group& g : b->grp) free_group(g);
+    if (b->na_staged) (void)hipEventDestroy(b->na_staged);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return rc == LBM_ETIMEOUT ? rc : LBM_OK;

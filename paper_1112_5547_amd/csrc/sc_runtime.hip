@@ -643,6 +643,8 @@ const char* lbm_sc_strerror(int status) {
         case LBM_ENONFINITE: return "non-finite density or velocity";
         case LBM_EBUDGET: return "batch memory budget exceeded";
         case LBM_ETIMEOUT: return "persistent launch hit its grid-barrier spin limit";
+        case LBM_ETOOBIG:
+            return "batch group exceeds the allocation-free scratch (1024 members, 262144 work items)";
         default: return "unknown status";
     }
 }
