@@ -44,3 +44,30 @@ def test_drop_128cube_fp32_against_fp64():
     assert c["max_abs_rho_A"] <= 1e-4
     assert abs(c["mass_drift_A_fp64"]) <= 1000 * 2.0 ** -52 * 8
     assert abs(c["R_eff_fp32"] - c["R_eff_fp64"]) <= 0.01 * c["R_eff_fp64"]
+
+
+@pytest.mark.gpu
+def test_spinodal_256cube_5000_steps_precision():
+    """The precision configuration: D3Q19 256^3 spinodal (G = 1.6, tau = 1,
+    seed 3), 5000 steps in FP64 and in FP32 shifted storage, compared at the
+    statistical level.  Bounds: domain lengths within 2 %; FP64 mass drift
+    within 8 roundings per step and |sum j| <= 1e-8; FP32 mass drift <= 2e-5
+    relative and the lattice momentum |sum j| <= 1e-9 N steps, i.e. an
+    average momentum bias under 1e-9 per site and step, about a hundredth of
+    an FP32 unit in the last place of the stored populations (|h| ~ 0.1)."""
+    from paper_1112_5547_amd.studies import spinodal_study
+    L, steps = 256, 5000
+    say("spinodal study 256^3, 5000 steps, fp64 and fp32_shifted")
+    r = spinodal_study(L=L, steps=steps, every=2500)
+    a, b = r["fp64"], r["fp32_shifted"]
+    say(f"domain lengths fp64 {[round(x['domain_length'], 3) for x in a]} "
+        f"fp32 {[round(x['domain_length'], 3) for x in b]}; momentum fp64 {a[-1]['mom']:.3e} "
+        f"fp32 {b[-1]['mom']:.3e}; mass drift fp64 {a[-1]['mass_drift_A']:.3e} "
+        f"fp32 {b[-1]['mass_drift_A']:.3e}")
+    assert a[-1]["domain_length"] > 10 * a[0]["domain_length"]      # coarsening happened
+    assert abs(b[-1]["domain_length"] - a[-1]["domain_length"]) <= 0.02 * a[-1]["domain_length"]
+    assert abs(a[-1]["mass_drift_A"]) <= steps * 2.0 ** -52 * 8
+    assert a[-1]["mom"] <= 1e-8
+    assert abs(b[-1]["mass_drift_A"]) <= 2e-5
+    assert b[-1]["mom"] <= 1e-9 * L ** 3 * steps
+    assert a[-1]["n_nonfinite"] == 0 and b[-1]["n_nonfinite"] == 0

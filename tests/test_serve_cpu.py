@@ -296,3 +296,34 @@ def test_aging_lets_a_waiting_large_job_ahead_of_new_small_ones():
                      aging=aging, nominal_rate=1e4).run(jobs)
         done[aging] = {r.job_id: r.completed for r in rep.results}
     assert done[4.0][0] < done[0.0][0] - 1.0
+
+
+def test_deadline_guard_keeps_each_job_near_its_arrival_order_completion():
+    """Pure SRPT lets a stream of small jobs pass a large one indefinitely; with
+    the deadline guard every job completes by about the time it would under
+    one-job-at-a-time service in arrival order at the nominal rate (plus an
+    epoch and the guard), while small jobs still overtake the large one as long
+    as it has slack (here the nominal rate is half the device's)."""
+    nominal = 0.5e4
+    res = {}
+    for guard in (None, 0.5):
+        clock = SimClock()
+        be = FakeBackend(clock, capacity=1e4)
+        # ten small jobs, then a large one, then a small one every 0.15 s
+        jobs = ([_job(k, 6, 30, 0.0) for k in range(1, 11)] + [_job(0, 30, 60, 0.001)]
+                + [_job(k, 6, 30, 0.15 * (k - 10)) for k in range(11, 160)])
+        rep = Server(hbm_budget=0, epoch_steps=10, backend=be, clock=clock, sat_sites=30,
+                     guard=guard, nominal_rate=nominal).run(jobs)
+        res[guard] = {r.job_id: r for r in rep.results}
+    v, deadline = 0.0, {}
+    for j in sorted(jobs, key=lambda j: j.arrival):
+        v = max(v, j.arrival) + j.sites * j.steps / nominal
+        deadline[j.job_id] = v
+    epoch_s = 10 * 30 * 30 / 1e4          # the longest epoch (the large job alone)
+    late_srpt = max(r.completed - deadline[k] for k, r in res[None].items())
+    late_guard = max(r.completed - deadline[k] for k, r in res[0.5].items())
+    assert late_srpt > 2.0                              # SRPT alone starves the large job
+    assert late_guard <= epoch_s + 0.5 + 0.1
+    # small jobs that arrive after the large one still overtake it while it has slack
+    later = [r for r in res[0.5].values() if r.arrival > 0.001]
+    assert sum(r.completed < res[0.5][0].completed for r in later) >= 5
