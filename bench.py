@@ -282,7 +282,7 @@ def serve_leg(n_jobs: int, budgets_gb, epoch: int):
            "batch_tiles": tiles, "mode": "fused", "epoch_steps": epoch, "runs": []}
     for gb in budgets_gb:
         server = Server(hbm_budget=int(gb * 1e9), epoch_steps=epoch, mode="fused", backend=be,
-                        tiles=tiles, policy="srpt", aging=0.0, guard=1.0,
+                        tiles=tiles, policy="srpt", aging=0.0, guard=0.2, share=0.3,
                         nominal_rate=capacity * 1e6)
         rep = server.run(jobs)
         served = rep.summary()
@@ -290,7 +290,7 @@ def serve_leg(n_jobs: int, budgets_gb, epoch: int):
                  f"p99 {served['p99_latency_s']:.2f} s, max queue {served['max_queue']}")
         out["runs"].append({
             "budget_gb": gb, "policy": server.policy, "sat_sites": server.sat_sites,
-            "guard_s": server.guard,
+            "guard_s": server.guard, "share": server.share,
             "nonfinite_jobs": [{"job": j.job_id, "tau": round(j.tau, 3), "G": round(j.G, 3)}
                                for j in jobs if j.job_id in served["nonfinite_jobs"]],
             "served": {k: r3(v) for k, v in served.items()}})

@@ -29,7 +29,12 @@ counts) arrive over time.  The loop:
       resident job whose slack against that deadline (deadline - now -
       remaining work) falls to ``guard`` seconds or less is served first,
       earliest deadline first, so that no job finishes much later than it
-      would have in arrival order while the others keep the SRPT order;
+      would have in arrival order while the others keep the SRPT order.
+      With ``share`` > 0 the non-urgent jobs keep that fraction of the device
+      time while urgent ones exist (epochs alternate, the urgent jobs' epochs
+      earning the others their share), and a job turns urgent
+      share / (1 - share) of its remaining work earlier, so that it still
+      meets its deadline on the rest of the time;
     - ``"all"``: every resident job advances every epoch (each job gets the
       same number of steps per epoch, whatever its size);
 * while an epoch runs on the device, prepares the next admissions on the host
@@ -163,7 +168,7 @@ class Server:
                  tiles: Optional[dict] = None, policy: str = "srpt",
                  sat_sites: int = 4_000_000, aging: float = 0.0,
                  nominal_rate: float = 1e10, solo_alone: bool = True,
-                 guard: Optional[float] = None):
+                 guard: Optional[float] = None, share: float = 0.0):
         if policy not in ("srpt", "all"):
             raise ValueError(f"unknown scheduling policy {policy!r}")
         self.policy = policy
@@ -172,6 +177,9 @@ class Server:
         self.solo_alone = bool(solo_alone)
         self.nominal_rate = float(nominal_rate)
         self.guard = None if guard is None else float(guard)
+        if not 0.0 <= share < 1.0:
+            raise ValueError("share must be in [0, 1)")
+        self.share = float(share)
         self.budget = int(hbm_budget)
         self.epoch_steps = int(epoch_steps)
         self.mode = mode
@@ -201,6 +209,8 @@ class Server:
             batch.set_tiles(self.tiles["tx9"], self.tiles["tx19"], self.tiles["ty19"],
                             self.tiles["mb9"], self.tiles["mb19"])
         epochs = 0
+        credit = 0.0       # device seconds owed to non-urgent jobs (deadline guard with a share)
+        phase = None       # "urgent" / "rest" / None: which jobs the current epoch serves
         need = {j.job_id: be.bytes_needed(j) for j in pending}
         # completion time of each job under one-job-at-a-time service in
         # arrival order at the nominal rate (depends on earlier arrivals only)
@@ -249,6 +259,8 @@ class Server:
             least remaining work, taken until their sites reach sat_sites.
             Returns the job to step alone when it is the only member and fills
             the device by itself, else None (the batch runs the epoch)."""
+            nonlocal phase
+            phase = None
             if not srpt:
                 return None
             now = clock.now()
@@ -260,13 +272,22 @@ class Server:
 
             order = sorted(resident, key=key)
             if self.guard is not None:
-                def slack(j):
-                    job = resident[j][0]
-                    return deadline[j] - now - remaining(j) * job.sites / self.nominal_rate
-                urgent = sorted((j for j in order if slack(j) <= self.guard),
+                lead = self.share / (1.0 - self.share)
+
+                def work_s(j):
+                    return remaining(j) * resident[j][0].sites / self.nominal_rate
+
+                urgent = sorted((j for j in order
+                                 if deadline[j] - now - work_s(j) <= self.guard + lead * work_s(j)),
                                 key=lambda j: (deadline[j], j))
                 late = set(urgent)
-                order = urgent + [j for j in order if j not in late]
+                rest = [j for j in order if j not in late]
+                if urgent and rest and credit > 0.0:
+                    order, phase = rest, "rest"          # the others' share of the time
+                elif urgent:
+                    order, phase = urgent + rest, "urgent"
+                else:
+                    order = rest
             chosen, sites = [], 0
             for jid in order:
                 n = resident[jid][0].sites
@@ -307,6 +328,7 @@ class Server:
                 clock.sleep_until(pending[0].arrival)
                 admit()
                 continue
+            t_epoch = clock.now()
             solo = schedule()
             if solo is not None:
                 lat = resident[solo][1]
@@ -324,6 +346,12 @@ class Server:
                 admit()                                    # host work overlaps the epoch
                 done = batch.poll()                        # waits for the epoch
             t_done = clock.now()
+            if phase == "urgent":
+                credit += (t_done - t_epoch) * self.share / (1.0 - self.share)
+            elif phase == "rest":
+                credit -= t_done - t_epoch
+            else:
+                credit = 0.0
             for lat in done:
                 jid = next(j for j, (_, l, _) in resident.items() if l is lat)
                 job, _, t_adm = resident.pop(jid)
