@@ -203,13 +203,14 @@ def batch_leg(n_jobs: int, steps: int, epoch: int):
     """64 independent D2Q9 drop lattices (L ~ U{64..512}, seed 4), FP32 shifted,
     advanced `steps` steps each: one launch per lattice per step (each lattice
     with its own autotuned kernel), one launch per step for all lattices
-    (graph-replayed), and one persistent launch per epoch, after the batch
+    (graph-replayed; the batch form the library and the server use), and one
+    persistent launch per epoch (reported beside it), after the batch
     autotuner picked the block shape and march chunks."""
     import torch
     import sc_inputs
     from paper_1112_5547_amd import Batch, Lattice, autotune
     jobs = sc_inputs.batch_jobs(n_jobs, seed=4, steps=steps)
-    tuned = autotune.tune_batch(jobs, precision="fp32_shifted", mode="persistent", epoch=50)
+    tuned = autotune.tune_batch(jobs, precision="fp32_shifted", mode="fused", epoch=50)
     work = sum(j.sites * j.steps for j in jobs)
     out = {"workload": f"{n_jobs} D2Q9 drop lattices L~U{{64..512}} (seed 4), FP32 shifted, "
                        f"{steps} steps each, epochs of {epoch}",
@@ -237,10 +238,9 @@ def batch_leg(n_jobs: int, steps: int, epoch: int):
             b.remove(lat)
             lat.close()
         b.close()
-    out["speedup_persistent_vs_per_lattice"] = round(
-        out["persistent"]["mlups"] / out["per_lattice"]["mlups"], 2)
     out["speedup_fused_vs_per_lattice"] = round(
         out["fused"]["mlups"] / out["per_lattice"]["mlups"], 2)
+    out["persistent_vs_fused"] = round(out["persistent"]["mlups"] / out["fused"]["mlups"], 2)
     return out
 
 

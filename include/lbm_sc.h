@@ -256,8 +256,10 @@ int lbm_sc_copy_bench(void *dst, const void *src, size_t nbytes, int reps, void 
 /* mode for lbm_batch_run */
 enum {
     LBM_BATCH_PER_LATTICE = 0, /* one launch per lattice per step (baseline) */
-    LBM_BATCH_FUSED = 1,       /* one launch per lattice group per step, all lattices */
-    LBM_BATCH_PERSISTENT = 2   /* one persistent launch per epoch with grid barriers */
+    LBM_BATCH_FUSED = 1,       /* one launch per lattice group per step, all lattices
+                                  (graph-replayed; the fastest form measured) */
+    LBM_BATCH_PERSISTENT = 2   /* one persistent launch per epoch with grid barriers
+                                  (for callers that want one launch per epoch) */
 };
 
 /* hbm_budget: bytes of member state the batch admits (0: unlimited).

@@ -160,7 +160,7 @@ if __name__ == "__main__":
 BATCH_CFGS = [(256, 64, 4), (256, 32, 8), (512, 64, 8), (128, 32, 4)]
 
 
-def tune_batch(jobs, *, precision: str = "fp32_shifted", mode: str = "persistent",
+def tune_batch(jobs, *, precision: str = "fp32_shifted", mode: str = "fused",
                epoch: int = 50, mbs=(0, 64, 256), verbose: bool = False) -> dict:
     """Chooses the shared block shape (D2Q9 tile width = D3Q19 tile area) and
     the march chunks of a batch by timing one epoch of the given jobs on

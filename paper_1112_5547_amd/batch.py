@@ -59,7 +59,7 @@ class Batch:
         check(lib().lbm_batch_remove(self._b, lat.handle), "batch_remove")
         self._members.pop(lat.handle.value, None)
 
-    def run(self, epoch_steps: int, mode: str = "persistent"):
+    def run(self, epoch_steps: int, mode: str = "fused"):
         check(lib().lbm_batch_run(self._b, int(epoch_steps), MODES[mode]), "batch_run")
 
     def run_noalloc(self, epoch_steps: int, mode: str = "fused"):

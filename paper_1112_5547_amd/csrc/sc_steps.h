@@ -333,17 +333,25 @@ k_batch_persistent(const BatchDesc* __restrict__ desc, const WorkItem* __restric
     __shared__ int s_flag;
     unsigned gen = 0;
     for (int k = 0; k < ksteps; ++k) {
-        for (;;) {
+        unsigned* ctr = &sync[SYNC_CTR + k];
+        if (threadIdx.x == 0)
+            s_item = (int)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        int it = s_item;
+        while (it < nwork) {
+            // the next claim is in flight while this item runs
+            int next = 0;
             if (threadIdx.x == 0)
-                s_item = (int)__hip_atomic_fetch_add(&sync[SYNC_CTR + k], 1u, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-            __syncthreads();
-            const int it = s_item;
-            __syncthreads();
-            if (it >= nwork) break;
+                next = (int)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
             const WorkItem w = work[it];
             const BatchDesc& d = desc[w.member];
             if (k < d.steps) BT::run(d, w, k, lds);
+            // every wave is done with this item's LDS ring and has read s_item
+            __syncthreads();
+            if (threadIdx.x == 0) s_item = next;
+            __syncthreads();
+            it = s_item;
         }
         if (k + 1 < ksteps && !grid_barrier(sync, gridDim.x, gen, &s_flag, spin_limit)) return;
     }

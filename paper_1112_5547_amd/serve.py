@@ -7,7 +7,7 @@ counts) arrive over time.  The loop:
 * admits queued jobs first-fit while the device-memory budget and the member
   slots allow (a job's state stays resident on the device until it finishes);
 * advances resident jobs in epochs of ``epoch_steps`` steps with one batch
-  launch per epoch (persistent, fused or per-lattice form).  Which resident
+  launch per epoch (fused, persistent or per-lattice form).  Which resident
   jobs an epoch advances is the scheduling policy:
     - ``"srpt"`` (default): shortest remaining work first.  Resident jobs are
       ordered by remaining site updates and taken until their lattices hold
@@ -162,7 +162,7 @@ class GpuBackend:
 
 
 class Server:
-    def __init__(self, hbm_budget: int = 0, *, epoch_steps: int = 200, mode: str = "persistent",
+    def __init__(self, hbm_budget: int = 0, *, epoch_steps: int = 200, mode: str = "fused",
                  max_resident: int = 256, backend=None, clock=None,
                  keep_populations: bool = False, admit_hook: Optional[Callable] = None,
                  tiles: Optional[dict] = None, policy: str = "srpt",
