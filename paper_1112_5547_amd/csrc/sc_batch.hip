@@ -261,7 +261,7 @@ int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vec
         BCALL(b, hipGetDeviceProperties(&prop, dev));
         BCALL(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)pf, b->nt, 0));
         if (per_cu < 1) return LBM_EDEVICE;
-        grid = std::min(nwork, per_cu * prop.multiProcessorCount);
+        grid = std::min(std::min(nwork, per_cu * prop.multiProcessorCount), kMaxPersistentBlocks);
     }
     // replay the cached graph when the launch shape is unchanged (the tables
     // are rewritten in place, so the captured arguments stay valid)

@@ -59,11 +59,19 @@ struct WorkItem {
     int member, tile_x, tile_y, chunk;
 };
 
-// sync words: [0] barrier count, [1] barrier generation, [2] timeout flag,
-// [3..3+K) per-step tile claim counters.  The timeout flag is sticky: the
+// sync words: [0] barrier count (block groups arrived), [1] barrier
+// generation, [2] timeout flag; from SYNC_GRP the arrival counters of the
+// block groups (kBarrierGroup blocks each, one 64-byte line per counter, so
+// that arrivals spread over many addresses instead of queueing on one); from
+// SYNC_CTR the per-step work claim counters.  The timeout flag is sticky: the
 // per-launch clear leaves it alone, so a give-up stays visible until the
 // host has read it.
-constexpr int SYNC_COUNT = 0, SYNC_GEN = 1, SYNC_TIMEOUT = 2, SYNC_CTR = 3;
+constexpr int kSyncLine = 16;  // words per 64-byte line
+constexpr int kBarrierGroup = 16, kBarrierGroups = 256;
+constexpr int kMaxPersistentBlocks = kBarrierGroup * kBarrierGroups;
+constexpr int SYNC_COUNT = 0, SYNC_GEN = 1, SYNC_TIMEOUT = 2;
+constexpr int SYNC_GRP = kSyncLine;
+constexpr int SYNC_CTR = SYNC_GRP + kBarrierGroups * kSyncLine;
 constexpr unsigned kSpinLimit = 1u << 26;  // ~seconds of s_sleep polling per barrier
 
 using BatchStepFn = void (*)(const BatchDesc*, const WorkItem*, int, int);

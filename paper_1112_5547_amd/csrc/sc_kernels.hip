@@ -5,7 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
-#include "sc_steps.h"
+#include "sc_batch_kernels.h"
 
 namespace sc {
 

@@ -1,9 +1,9 @@
-// sc_steps.h -- the step kernels and the batch kernels, templated on the
-// policy (storage precision, forcing scheme, relaxation), with their host
+// sc_steps.h -- the single-lattice step kernels, templated on the policy
+// (storage precision, forcing scheme, relaxation), with their host
 // launchers.  Each policy is instantiated in a translation unit of its own
 // (sc_step_<policy>.hip), so that the policies compile in parallel and no
-// policy carries another's code; the runtime and the batch engine reach
-// them through step_launch<P> / batch_fns<P>.
+// policy carries another's code; the runtime reaches them through
+// step_launch<P>.  The batch kernels are in sc_batch_kernels.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -242,140 +242,6 @@ static hipError_t launch_twopass_t(const StepParams& p, void* psi, hipStream_t s
 }
 
 
-// ---------------------------------------------------------------------------
-// Batched forms: one launch per step over the work items of many lattices,
-// or one persistent launch per epoch with a grid barrier between steps.
-// ---------------------------------------------------------------------------
-
-template <class PR, int NT, int TX19, int TY19>
-struct BatchTiles {
-    using T9 = TileStep<9, PR, NT, 1>;
-    using T19 = TileStep<19, PR, TX19, TY19>;
-    static_assert(TX19 * TY19 == NT, "both lattice types use the block size");
-    static constexpr int LDS_ELEMS =
-        T9::LDS_ELEMS > T19::LDS_ELEMS ? T9::LDS_ELEMS : T19::LDS_ELEMS;
-    __device__ static __forceinline__ void run(const BatchDesc& d, const WorkItem& w, int k,
-                               typename PR::A* lds) {
-        const int parity = d.base_parity ^ (k & 1);
-        if (d.Q == 9)
-            T9::run(d.sp[parity], w.tile_x, w.tile_y, w.chunk, lds);
-        else
-            T19::run(d.sp[parity], w.tile_x, w.tile_y, w.chunk, lds);
-    }
-};
-
-template <class PR>
-struct BatchWaves {
-    static constexpr int value = PR::shifted ? 3 : 2;
-};
-
-template <class PR, int NT, int TX19, int TY19>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<PR>::value)))
-k_batch_step(const BatchDesc* __restrict__ desc, const WorkItem* __restrict__ work, int nwork,
-             int k) {
-    using BT = BatchTiles<PR, NT, TX19, TY19>;
-    __shared__ typename PR::A lds[BT::LDS_ELEMS];
-    const int it = (int)blockIdx.x;
-    if (it >= nwork) return;
-    const WorkItem w = work[it];
-    const BatchDesc& d = desc[w.member];
-    if (k >= d.steps) return;
-    BT::run(d, w, k, lds);
-}
-
-__device__ __forceinline__ unsigned ld_acquire(unsigned* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Grid-wide barrier for co-resident blocks; returns false if the wait hit
-// the spin limit or another block already reported a timeout (all blocks
-// then leave the kernel, so every wave terminates).
-__device__ inline bool grid_barrier(unsigned* sync, unsigned nblocks, unsigned& gen, int* s_flag,
-                                    unsigned spin_limit) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        const unsigned g = gen;
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&sync[SYNC_COUNT], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&sync[SYNC_COUNT], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sync[SYNC_GEN], g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned spins = 0;
-            while (ld_acquire(&sync[SYNC_GEN]) == g) {
-                if (ld_acquire(&sync[SYNC_TIMEOUT]) != 0u || ++spins > spin_limit) {
-                    __hip_atomic_store(&sync[SYNC_TIMEOUT], 1u, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-        }
-        gen = g + 1;
-        *s_flag = ok;
-    }
-    __syncthreads();
-    const bool ok = *s_flag != 0;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return ok;
-}
-
-template <class PR, int NT, int TX19, int TY19>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<PR>::value)))
-k_batch_persistent(const BatchDesc* __restrict__ desc, const WorkItem* __restrict__ work,
-                   int nwork, int ksteps, unsigned* sync, unsigned spin_limit) {
-    using BT = BatchTiles<PR, NT, TX19, TY19>;
-    __shared__ typename PR::A lds[BT::LDS_ELEMS];
-    __shared__ int s_item;
-    __shared__ int s_flag;
-    unsigned gen = 0;
-    for (int k = 0; k < ksteps; ++k) {
-        unsigned* ctr = &sync[SYNC_CTR + k];
-        if (threadIdx.x == 0)
-            s_item = (int)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        int it = s_item;
-        while (it < nwork) {
-            // the next claim is in flight while this item runs
-            int next = 0;
-            if (threadIdx.x == 0)
-                next = (int)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-            const WorkItem w = work[it];
-            const BatchDesc& d = desc[w.member];
-            if (k < d.steps) BT::run(d, w, k, lds);
-            // every wave is done with this item's LDS ring and has read s_item
-            __syncthreads();
-            if (threadIdx.x == 0) s_item = next;
-            __syncthreads();
-            it = s_item;
-        }
-        if (k + 1 < ksteps && !grid_barrier(sync, gridDim.x, gen, &s_flag, spin_limit)) return;
-    }
-}
-
-template <class PR>
-bool batch_fns(int nt, int tx19, int ty19, BatchStepFn* sf, BatchPersFn* pf) {
-#define SC_CFG(NT_, X_, Y_)                                          \
-    if (nt == NT_ && tx19 == X_ && ty19 == Y_) {                     \
-        *sf = k_batch_step<PR, NT_, X_, Y_>;                         \
-        *pf = k_batch_persistent<PR, NT_, X_, Y_>;                   \
-        return true;                                                 \
-    }
-    SC_CFG(256, 64, 4)
-    SC_CFG(256, 32, 8)
-    SC_CFG(256, 16, 16)
-    SC_CFG(128, 32, 4)
-    SC_CFG(512, 64, 8)
-    SC_CFG(512, 32, 16)
-#undef SC_CFG
-    return false;
-}
-
-
 // Single-lattice step of one policy: variant 0 fused, 1 two-pass, 2 pipelined,
 // 3 re-pull (psi is the two-pass density array).
 template <class PR>
@@ -393,8 +259,7 @@ hipError_t step_launch(int variant, int Q, int tx, int ty, const StepParams& p, 
 #define SC_POLICIES(X) X(PF64) X(PF32S) X(PF64G) X(PF32SG) X(PF64T) X(PF32ST) X(PF64GT) X(PF32SGT)
 #define SC_DECLARE(P)                                                                        \
     extern template hipError_t step_launch<P>(int, int, int, int, const StepParams&, void*, \
-                                              hipStream_t);                                 \
-    extern template bool batch_fns<P>(int, int, int, BatchStepFn*, BatchPersFn*);
+                                              hipStream_t);
 SC_POLICIES(SC_DECLARE)
 #undef SC_DECLARE
 
