@@ -204,17 +204,19 @@ def batch_leg(n_jobs: int, steps: int, epoch: int):
     advanced `steps` steps each: one launch per lattice per step (each lattice
     with its own autotuned kernel), one launch per step for all lattices
     (graph-replayed; the batch form the library and the server use), and one
-    persistent launch per epoch (reported beside it), after the batch
-    autotuner picked the block shape and march chunks."""
+    persistent launch per epoch (reported beside it), each form with the block
+    shape and march chunks the batch autotuner picked for it."""
     import torch
     import sc_inputs
     from paper_1112_5547_amd import Batch, Lattice, autotune
     jobs = sc_inputs.batch_jobs(n_jobs, seed=4, steps=steps)
-    tuned = autotune.tune_batch(jobs, precision="fp32_shifted", mode="fused", epoch=50)
+    tuned = {m: autotune.tune_batch(jobs, precision="fp32_shifted", mode=m, epoch=50)
+             for m in ("fused", "persistent")}
+    tuned["per_lattice"] = tuned["fused"]
     work = sum(j.sites * j.steps for j in jobs)
     out = {"workload": f"{n_jobs} D2Q9 drop lattices L~U{{64..512}} (seed 4), FP32 shifted, "
                        f"{steps} steps each, epochs of {epoch}",
-           "site_updates": work, "tiles": tuned}
+           "site_updates": work, "tiles": tuned["fused"], "tiles_persistent": tuned["persistent"]}
     for mode in ("per_lattice", "fused", "persistent"):
         lats = []
         for j in jobs:
@@ -225,7 +227,8 @@ def batch_leg(n_jobs: int, steps: int, epoch: int):
             lat.init(fl.rho_A, fl.rho_B)
             lats.append(lat)
         b = Batch()
-        b.set_tiles(tuned["tx9"], tuned["tx19"], tuned["ty19"], tuned["mb9"], tuned["mb19"])
+        t = tuned[mode]
+        b.set_tiles(t["tx9"], t["tx19"], t["ty19"], t["mb9"], t["mb19"])
         for lat, j in zip(lats, jobs):
             b.add(lat, j.steps)
         torch.cuda.synchronize()
@@ -250,11 +253,16 @@ def serve_leg(n_jobs: int, budgets_gb, epoch: int):
     U{500..5000}, FP32 shifted.  The arrival rate offers 0.7 x the capacity of
     one-job-at-a-time service for this job mix (solo step times measured per
     lattice shape).  Served with continuous batching (shortest remaining work
-    first, with a deadline guard: a job whose slack against its completion
-    time under one-job-at-a-time service in arrival order runs out is served
-    first; device-filling lattices and lone jobs step with their tuned solo
-    kernels) under each memory budget, and sequentially (one job at a time,
-    one lattice per launch, arrival order) on the same arrivals."""
+    first on the slack of a deadline guard: each job's deadline is its
+    completion time under one-job-at-a-time service in arrival order at the
+    measured solo step times, and when the earliest-deadline-first schedule
+    of the resident jobs has less than the guard's slack left, epochs serve
+    the deadline order; the guard of -0.5 s lets a job finish up to about
+    half a second plus an epoch after its deadline, which the shortest-work
+    order spends on the median; device-filling lattices and lone jobs step with
+    their tuned solo kernels) under each memory budget, and sequentially (one
+    job at a time, one lattice per launch, arrival order) on the same
+    arrivals."""
     import sc_inputs
     from paper_1112_5547_amd import autotune
     from paper_1112_5547_amd.serve import (GpuBackend, Server, offered_rate, sequential_baseline,
@@ -282,15 +290,15 @@ def serve_leg(n_jobs: int, budgets_gb, epoch: int):
            "batch_tiles": tiles, "mode": "fused", "epoch_steps": epoch, "runs": []}
     for gb in budgets_gb:
         server = Server(hbm_budget=int(gb * 1e9), epoch_steps=epoch, mode="fused", backend=be,
-                        tiles=tiles, policy="srpt", aging=0.0, guard=0.2, share=0.3,
-                        nominal_rate=capacity * 1e6)
+                        tiles=tiles, policy="srpt", aging=0.0, guard=-0.5,
+                        nominal_rate=capacity * 1e6, step_seconds=step_s)
         rep = server.run(jobs)
         served = rep.summary()
         progress(f"serving: {gb:g} GB budget: p50 {served['p50_latency_s']:.2f} s, "
                  f"p99 {served['p99_latency_s']:.2f} s, max queue {served['max_queue']}")
         out["runs"].append({
             "budget_gb": gb, "policy": server.policy, "sat_sites": server.sat_sites,
-            "guard_s": server.guard, "share": server.share,
+            "guard_s": server.guard,
             "nonfinite_jobs": [{"job": j.job_id, "tau": round(j.tau, 3), "G": round(j.G, 3)}
                                for j in jobs if j.job_id in served["nonfinite_jobs"]],
             "served": {k: r3(v) for k, v in served.items()}})

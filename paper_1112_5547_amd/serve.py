@@ -19,22 +19,26 @@ counts) arrive over time.  The loop:
       at full rate once it is the shortest.  An epoch whose only member fills
       the device by itself (at least ``sat_sites`` sites) steps that lattice
       alone with its own tuned kernel instead of the batch launch, and so
-      does any lone member (``solo_alone``, the default).  With
-      ``aging`` > 0 the order key is the remaining work in seconds (at
-      ``nominal_rate`` site updates per second) minus ``aging`` times the time
+      does any lone member (``solo_alone``, the default).  Work is priced
+      in seconds of solo service: a job's remaining steps times its lattice
+      shape's measured solo step time (``step_seconds``, keyed by
+      (lattice, nx, ny, nz)), or its remaining site updates at
+      ``nominal_rate`` for shapes without one.  With ``aging`` > 0 the order
+      key is the remaining work minus ``aging`` times the time
       the job has spent in the system, so that a large job cannot be passed
       over indefinitely by a stream of smaller ones.  With ``guard`` set,
-      every job also carries the completion time it would have under
-      one-job-at-a-time service in arrival order (at ``nominal_rate``); a
-      resident job whose slack against that deadline (deadline - now -
-      remaining work) falls to ``guard`` seconds or less is served first,
-      earliest deadline first, so that no job finishes much later than it
-      would have in arrival order while the others keep the SRPT order.
-      With ``share`` > 0 the non-urgent jobs keep that fraction of the device
-      time while urgent ones exist (epochs alternate, the urgent jobs' epochs
-      earning the others their share), and a job turns urgent
-      share / (1 - share) of its remaining work earlier, so that it still
-      meets its deadline on the rest of the time;
+      every job also carries a deadline, the completion time it would have
+      under one-job-at-a-time service in arrival order (at those prices),
+      and the SRPT order only runs on the slack of the deadlines: before
+      each epoch the server takes the resident jobs in deadline order and
+      the least, over that order, of a job's deadline minus now minus the
+      remaining work of it and of the jobs due before it.  While that slack
+      exceeds ``guard`` seconds the epoch keeps the SRPT order; otherwise it
+      serves the deadline order (earliest deadline first), which meets every
+      deadline the slack still allows.  No job then finishes much later
+      than it would have in arrival order (by about an epoch and the guard,
+      with the service prices right), while small jobs overtake large ones
+      whenever the deadlines leave room;
     - ``"all"``: every resident job advances every epoch (each job gets the
       same number of steps per epoch, whatever its size);
 * while an epoch runs on the device, prepares the next admissions on the host
@@ -88,6 +92,7 @@ class ServeReport:
     epochs: int
     queue_depth: List[tuple]    # (time, queued, resident)
     refused: int                # jobs that can never fit the budget
+    deadline_epochs: int = 0    # epochs served in deadline order (guard)
 
     def latencies(self) -> np.ndarray:
         return np.array([r.latency for r in self.results])
@@ -103,6 +108,7 @@ class ServeReport:
             "makespan_s": self.makespan,
             "aggregate_mlups": su / self.makespan / 1e6 if self.makespan > 0 else None,
             "epochs": self.epochs,
+            "deadline_epochs": self.deadline_epochs,
             "max_queue": max((q for _, q, _ in self.queue_depth), default=0),
             "max_resident": max((r for _, _, r in self.queue_depth), default=0),
             "nonfinite": sum(r.status != "ok" for r in self.results),
@@ -168,7 +174,8 @@ class Server:
                  tiles: Optional[dict] = None, policy: str = "srpt",
                  sat_sites: int = 4_000_000, aging: float = 0.0,
                  nominal_rate: float = 1e10, solo_alone: bool = True,
-                 guard: Optional[float] = None, share: float = 0.0):
+                 guard: Optional[float] = None,
+                 step_seconds: Optional[Dict[tuple, float]] = None):
         if policy not in ("srpt", "all"):
             raise ValueError(f"unknown scheduling policy {policy!r}")
         self.policy = policy
@@ -176,10 +183,8 @@ class Server:
         self.aging = float(aging)
         self.solo_alone = bool(solo_alone)
         self.nominal_rate = float(nominal_rate)
+        self.step_seconds = dict(step_seconds) if step_seconds else {}
         self.guard = None if guard is None else float(guard)
-        if not 0.0 <= share < 1.0:
-            raise ValueError("share must be in [0, 1)")
-        self.share = float(share)
         self.budget = int(hbm_budget)
         self.epoch_steps = int(epoch_steps)
         self.mode = mode
@@ -189,6 +194,15 @@ class Server:
         self.keep_populations = keep_populations
         self.admit_hook = admit_hook
         self.tiles = tiles
+
+    def service_s(self, job, steps: int) -> float:
+        """Seconds of `steps` steps of `job` served alone: its lattice shape's
+        measured solo step time when known, else its site updates at the
+        nominal rate."""
+        t = self.step_seconds.get((job.lattice, job.nx, job.ny, job.nz))
+        if t is not None:
+            return steps * t
+        return steps * job.sites / self.nominal_rate
 
     def run(self, jobs: Sequence) -> ServeReport:
         be, clock = self.backend, self.clock
@@ -209,15 +223,15 @@ class Server:
             batch.set_tiles(self.tiles["tx9"], self.tiles["tx19"], self.tiles["ty19"],
                             self.tiles["mb9"], self.tiles["mb19"])
         epochs = 0
-        credit = 0.0       # device seconds owed to non-urgent jobs (deadline guard with a share)
-        phase = None       # "urgent" / "rest" / None: which jobs the current epoch serves
+        deadline_epochs = 0   # epochs the guard put in deadline order
+        phase = None       # "deadline" when the guard put the epoch in deadline order
         need = {j.job_id: be.bytes_needed(j) for j in pending}
         # completion time of each job under one-job-at-a-time service in
-        # arrival order at the nominal rate (depends on earlier arrivals only)
+        # arrival order (depends on earlier arrivals only)
         deadline: Dict[int, float] = {}
         v = 0.0
         for j in pending:
-            v = max(v, j.arrival) + j.sites * j.steps / self.nominal_rate
+            v = max(v, j.arrival) + self.service_s(j, j.steps)
             deadline[j.job_id] = v
 
         def admit():
@@ -267,27 +281,23 @@ class Server:
 
             def key(j):
                 job = resident[j][0]
-                work_s = remaining(j) * job.sites / self.nominal_rate
+                work_s = self.service_s(job, remaining(j))
                 return (work_s - self.aging * (now - job.arrival), job.arrival, j)
 
             order = sorted(resident, key=key)
             if self.guard is not None:
-                lead = self.share / (1.0 - self.share)
-
-                def work_s(j):
-                    return remaining(j) * resident[j][0].sites / self.nominal_rate
-
-                urgent = sorted((j for j in order
-                                 if deadline[j] - now - work_s(j) <= self.guard + lead * work_s(j)),
-                                key=lambda j: (deadline[j], j))
-                late = set(urgent)
-                rest = [j for j in order if j not in late]
-                if urgent and rest and credit > 0.0:
-                    order, phase = rest, "rest"          # the others' share of the time
-                elif urgent:
-                    order, phase = urgent + rest, "urgent"
-                else:
-                    order = rest
+                # slack of the earliest-deadline-first schedule of the resident
+                # jobs: the least, over the deadline order, of a job's deadline
+                # minus now minus the remaining work of it and of every job due
+                # before it.  Above the guard an epoch in SRPT order can be
+                # spared; at or below it the epoch serves the deadline order.
+                by_deadline = sorted(resident, key=lambda j: (deadline[j], j))
+                cum, slack = 0.0, float("inf")
+                for j in by_deadline:
+                    cum += self.service_s(resident[j][0], remaining(j))
+                    slack = min(slack, deadline[j] - now - cum)
+                if slack <= self.guard:
+                    order, phase = by_deadline, "deadline"
             chosen, sites = [], 0
             for jid in order:
                 n = resident[jid][0].sites
@@ -328,7 +338,6 @@ class Server:
                 clock.sleep_until(pending[0].arrival)
                 admit()
                 continue
-            t_epoch = clock.now()
             solo = schedule()
             if solo is not None:
                 lat = resident[solo][1]
@@ -346,12 +355,8 @@ class Server:
                 admit()                                    # host work overlaps the epoch
                 done = batch.poll()                        # waits for the epoch
             t_done = clock.now()
-            if phase == "urgent":
-                credit += (t_done - t_epoch) * self.share / (1.0 - self.share)
-            elif phase == "rest":
-                credit -= t_done - t_epoch
-            else:
-                credit = 0.0
+            if phase == "deadline":
+                deadline_epochs += 1
             for lat in done:
                 jid = next(j for j, (_, l, _) in resident.items() if l is lat)
                 job, _, t_adm = resident.pop(jid)
@@ -371,7 +376,7 @@ class Server:
         if hasattr(batch, "close"):
             batch.close()
         results.sort(key=lambda r: r.job_id)
-        return ServeReport(results, makespan, epochs, depth, refused)
+        return ServeReport(results, makespan, epochs, depth, refused, deadline_epochs)
 
 
 def solo_step_seconds(jobs, backend=None, *, warm: int = 32, timed: int = 64) -> Dict[tuple, float]:

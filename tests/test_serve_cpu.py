@@ -301,12 +301,13 @@ def test_aging_lets_a_waiting_large_job_ahead_of_new_small_ones():
 def test_deadline_guard_keeps_each_job_near_its_arrival_order_completion():
     """Pure SRPT lets a stream of small jobs pass a large one indefinitely; with
     the deadline guard every job completes by about the time it would under
-    one-job-at-a-time service in arrival order at the nominal rate (plus an
-    epoch and the guard), while small jobs still overtake the large one as long
-    as it has slack (here the nominal rate is half the device's)."""
+    one-job-at-a-time service in arrival order at the nominal rate (within an
+    epoch for a guard >= 0, within an epoch plus |guard| for a negative one),
+    while small jobs still overtake the large one as long as the deadlines
+    leave slack (here the nominal rate is half the device's)."""
     nominal = 0.5e4
     res = {}
-    for guard in (None, 0.5):
+    for guard in (None, 0.5, -1.0):
         clock = SimClock()
         be = FakeBackend(clock, capacity=1e4)
         # ten small jobs, then a large one, then a small one every 0.15 s
@@ -322,8 +323,45 @@ def test_deadline_guard_keeps_each_job_near_its_arrival_order_completion():
     epoch_s = 10 * 30 * 30 / 1e4          # the longest epoch (the large job alone)
     late_srpt = max(r.completed - deadline[k] for k, r in res[None].items())
     late_guard = max(r.completed - deadline[k] for k, r in res[0.5].items())
+    late_neg = max(r.completed - deadline[k] for k, r in res[-1.0].items())
     assert late_srpt > 2.0                              # SRPT alone starves the large job
-    assert late_guard <= epoch_s + 0.5 + 0.1
+    assert late_guard <= epoch_s + 0.1
+    assert late_neg <= epoch_s + 1.0 + 0.1
+    assert late_neg > late_guard                        # the allowance is used
     # small jobs that arrive after the large one still overtake it while it has slack
-    later = [r for r in res[0.5].values() if r.arrival > 0.001]
-    assert sum(r.completed < res[0.5][0].completed for r in later) >= 5
+    for g in (0.5, -1.0):
+        later = [r for r in res[g].values() if r.arrival > 0.001]
+        assert sum(r.completed < res[g][0].completed for r in later) >= 5
+
+
+def test_deadline_guard_backlog_of_due_jobs():
+    """Several large jobs that are due on arrival (the device is behind their
+    arrival-order completion times) are served in deadline order ahead of a
+    stream of small jobs: the guard looks at the cumulative work of the jobs
+    due first, not at each job alone."""
+    nominal = 1e4
+    clock = SimClock()
+    be = FakeBackend(clock, capacity=1e4)
+    jobs = ([_job(k, 30, 40, 0.001 * k) for k in range(3)]
+            + [_job(k, 6, 20, 0.05 * (k - 2)) for k in range(3, 80)])
+    rep = Server(hbm_budget=0, epoch_steps=10, backend=be, clock=clock, sat_sites=30,
+                 guard=0.0, nominal_rate=nominal).run(jobs)
+    v, deadline = 0.0, {}
+    for j in sorted(jobs, key=lambda j: j.arrival):
+        v = max(v, j.arrival) + j.sites * j.steps / nominal
+        deadline[j.job_id] = v
+    epoch_s = 10 * 30 * 30 / 1e4
+    assert max(r.completed - deadline[r.job_id] for r in rep.results) <= epoch_s + 0.1
+    assert rep.summary()["deadline_epochs"] > 0
+
+
+def test_service_prices_from_solo_step_times():
+    """With measured solo step times the server prices a job by its shape's
+    step time, else by its site updates at the nominal rate."""
+    clock = SimClock()
+    be = FakeBackend(clock, capacity=1e4)
+    a, b = _job(0, 30, 40, 0.0), _job(1, 6, 20, 0.0)
+    srv = Server(backend=be, clock=clock, nominal_rate=1e4,
+                 step_seconds={(a.lattice, a.nx, a.ny, a.nz): 2e-3})
+    assert srv.service_s(a, 40) == pytest.approx(40 * 2e-3)
+    assert srv.service_s(b, 20) == pytest.approx(20 * b.sites / 1e4)
