@@ -120,7 +120,8 @@ def b_alg(q: int, esize: int) -> int:
     return 2 * q * 2 * esize
 
 
-def time_lattice(fields, precision, steps, warmup, kernel=None, forcing="shift", tau_minus=None):
+def time_lattice(fields, precision, steps, warmup, kernel=None, forcing="shift", tau_minus=None,
+                 repeats=0):
     import torch
     from paper_1112_5547_amd import Lattice, autotune
     lat = Lattice(Q19, L, L, L, tau_A=TAU, tau_B=TAU, G=G, precision=precision, forcing=forcing,
@@ -140,11 +141,23 @@ def time_lattice(fields, precision, steps, warmup, kernel=None, forcing="shift",
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     T = lat.totals()
+    # further samples of the same number of steps after the timed region (the
+    # spread of the step time on this machine; value and roofline keep the first)
+    again = [lat.time_steps(steps) / steps for _ in range(repeats)]
     kern = lat.kernel
     lat.close()
     del lat
     torch.cuda.empty_cache()
-    return {"wall_s": wall, "kernel_ms": ms_events / steps, "T0": T0, "T": T, "kernel": kern}
+    return {"wall_s": wall, "kernel_ms": ms_events / steps, "T0": T0, "T": T, "kernel": kern,
+            "repeats_ms": again}
+
+
+def repeat_summary(r) -> dict:
+    import statistics
+    ms = [r["kernel_ms"]] + r["repeats_ms"]
+    return {"samples": len(ms), "kernel_ms": [round(v, 4) for v in ms],
+            "median_ms": round(statistics.median(ms), 4),
+            "spread": round((max(ms) - min(ms)) / statistics.median(ms), 4)}
 
 
 def cpu_model() -> str:
@@ -345,7 +358,7 @@ def main():
     n = L ** 3
 
     kernel = tuple(int(v) for v in args.kernel.split(",")) if args.kernel else None
-    r64 = time_lattice(fields, "fp64", args.steps, args.warmup, kernel)
+    r64 = time_lattice(fields, "fp64", args.steps, args.warmup, kernel, repeats=4)
     mlups = n * args.steps / r64["wall_s"] / 1e6
     ach = b_alg(Q19, 8) * n / (r64["kernel_ms"] * 1e-3) / 1e9
     sym64 = kernel_symbol(r64["kernel"], "fp64")
@@ -374,9 +387,10 @@ def main():
                      "bytes_per_site": b_alg(Q19, 8)},
         "checks": {"mass_drift_A": (r64["T"]["mass_A"] - r64["T0"]["mass_A"]) / r64["T0"]["mass_A"],
                    "mom_x": r64["T"]["mom_x"], "max_u": r64["T"]["max_u"]},
+        "repeats": repeat_summary(r64),
     }
     if not args.no_fp32:
-        r32 = time_lattice(fields, "fp32_shifted", args.steps, args.warmup)
+        r32 = time_lattice(fields, "fp32_shifted", args.steps, args.warmup, repeats=4)
         ach32 = b_alg(Q19, 4) * n / (r32["kernel_ms"] * 1e-3) / 1e9
         sym32 = kernel_symbol(r32["kernel"], "fp32_shifted")
         traffic32, tbytes32 = traffic_for(sym32, r32["kernel_ms"])
@@ -389,7 +403,7 @@ def main():
                          "traffic": None if traffic32 is None else round(traffic32, 1),
                          "traffic_bytes_per_launch": tbytes32, "kernel": sym32,
                          "kernel_ms": round(r32["kernel_ms"], 4), "bytes_per_site": b_alg(Q19, 4)},
-            "kernel": list(r32["kernel"]),
+            "kernel": list(r32["kernel"]), "repeats": repeat_summary(r32),
             "mass_drift_A": (r32["T"]["mass_A"] - r32["T0"]["mass_A"]) / r32["T0"]["mass_A"],
         }
     if not args.no_schemes:
