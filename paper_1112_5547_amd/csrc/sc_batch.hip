@@ -64,6 +64,9 @@ struct Group {
     hipGraphExec_t gexec = nullptr;
     int g_mode = -1, g_nwork = -1, g_k = -1, g_grid = -1;
     unsigned g_spin = 0;
+    // launch shape of the last epoch (captured or launched directly)
+    int l_mode = -1, l_nwork = -1, l_k = -1, l_grid = -1;
+    unsigned l_spin = 0;
     bool pers_used = false;       // a persistent launch may have set the timeout flag
 };
 
@@ -263,14 +266,8 @@ int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vec
         if (per_cu < 1) return LBM_EDEVICE;
         grid = std::min(std::min(nwork, per_cu * prop.multiProcessorCount), kMaxPersistentBlocks);
     }
-    // replay the cached graph when the launch shape is unchanged (the tables
-    // are rewritten in place, so the captured arguments stay valid)
-    if (!(g.gexec && g.g_mode == mode && g.g_nwork == nwork && g.g_k == K && g.g_grid == grid &&
-          g.g_spin == b->spin_limit)) {
-        if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
-        g.gexec = nullptr;
-        hipGraph_t graph = nullptr;
-        BCALL(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    // the epoch's launches (into a capture, or straight onto the stream)
+    auto enqueue = [&]() -> hipError_t {
         hipError_t le = hipSuccess;
         if (mode == LBM_BATCH_FUSED) {
             for (int k = 0; k < K && le == hipSuccess; ++k) {
@@ -287,6 +284,38 @@ int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vec
                 le = hipGetLastError();
             }
         }
+        return le;
+    };
+    if (mode == LBM_BATCH_PERSISTENT) g.pers_used = true;
+    // replay the cached graph when the launch shape is unchanged (the tables
+    // are rewritten in place, so the captured arguments stay valid)
+    const bool cached = g.gexec && g.g_mode == mode && g.g_nwork == nwork && g.g_k == K &&
+                        g.g_grid == grid && g.g_spin == b->spin_limit;
+    const bool repeat = g.l_mode == mode && g.l_nwork == nwork && g.l_k == K && g.l_grid == grid &&
+                        g.l_spin == b->spin_limit;
+    g.l_mode = mode;
+    g.l_nwork = nwork;
+    g.l_k = K;
+    g.l_grid = grid;
+    g.l_spin = b->spin_limit;
+    if (!cached && !repeat) {
+        // a launch shape not seen in the last epoch (the members changed):
+        // launch directly, since capturing and instantiating a graph costs
+        // about a millisecond of host time while the device waits; the graph
+        // is captured once the shape repeats
+        const hipError_t le = enqueue();
+        if (le != hipSuccess) {
+            b->err = LBM_EDEVICE;
+            return LBM_EDEVICE;
+        }
+        return LBM_OK;
+    }
+    if (!cached) {
+        if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+        g.gexec = nullptr;
+        hipGraph_t graph = nullptr;
+        BCALL(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t le = enqueue();
         hipError_t ee = hipStreamEndCapture(b->stream, &graph);
         if (le != hipSuccess || ee != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -306,7 +335,6 @@ int run_group(lbm_batch* b, int pol, const std::vector<int>& idx, const std::vec
         g.g_grid = grid;
         g.g_spin = b->spin_limit;
     }
-    if (mode == LBM_BATCH_PERSISTENT) g.pers_used = true;
     BCALL(b, hipGraphLaunch(g.gexec, b->stream));
     return LBM_OK;
 }
