@@ -10,7 +10,7 @@ counts) arrive over time.  The loop:
   launch per epoch (fused, persistent or per-lattice form).  Which resident
   jobs an epoch advances is the scheduling policy:
     - ``"srpt"`` (default): shortest remaining work first.  Resident jobs are
-      ordered by remaining site updates and taken until their lattices hold
+      ordered by remaining work (priced as below) and taken until their lattices hold
       ``sat_sites`` sites, the size at which one batch launch keeps the whole
       device busy; the rest wait, resident, for a later epoch.  A lattice of
       ``sat_sites`` or more never joins a batch: the prefix stops before it,
@@ -36,8 +36,9 @@ counts) arrive over time.  The loop:
       exceeds ``guard`` seconds the epoch keeps the SRPT order; otherwise it
       serves the deadline order (earliest deadline first), which meets every
       deadline the slack still allows.  No job then finishes much later
-      than it would have in arrival order (by about an epoch and the guard,
-      with the service prices right), while small jobs overtake large ones
+      than it would have in arrival order (by about an epoch with a guard
+      of 0 or more, by about an epoch plus |guard| with a negative one, the
+      service prices being right), while small jobs overtake large ones
       whenever the deadlines leave room;
     - ``"all"``: every resident job advances every epoch (each job gets the
       same number of steps per epoch, whatever its size);
