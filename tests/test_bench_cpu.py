@@ -34,6 +34,18 @@ def test_algorithmic_bytes_per_site_update(bench):
     assert bench.b_alg(9, 8) == 288 and bench.b_alg(9, 4) == 144
 
 
+def test_repeat_summary_keeps_the_timed_sample_first(bench):
+    """The timed region's step time comes first; the median and the spread
+    (max - min over the median) cover it and the later samples."""
+    r = {"kernel_ms": 2.20, "repeats_ms": [2.18, 2.19, 2.30, 2.21]}
+    s = bench.repeat_summary(r)
+    assert s["samples"] == 5 and s["kernel_ms"][0] == 2.2
+    assert s["median_ms"] == 2.2
+    assert s["spread"] == pytest.approx((2.30 - 2.18) / 2.20, abs=1e-4)
+    assert bench.repeat_summary({"kernel_ms": 1.0, "repeats_ms": []}) == {
+        "samples": 1, "kernel_ms": [1.0], "median_ms": 1.0, "spread": 0.0}
+
+
 def test_tuned_kernels_have_recorded_traffic(bench):
     """The kernels bench.py times on the 256^3 workload (from the autotune
     table) are the ones whose counters profiles/traffic.json holds, under the
