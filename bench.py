@@ -263,48 +263,46 @@ def batch_leg(n_jobs: int, steps: int, epoch: int):
 def serve_leg(n_jobs: int, budgets_gb, epoch: int):
     """Poisson stream of drop / spinodal jobs (seed 5): 70 % D2Q9 drops
     L~U{64..512}, 30 % D3Q19 L~U{64..256} (half drops, half spinodal), steps
-    U{500..5000}, FP32 shifted.  The arrival rate offers 0.7 x the capacity of
-    one-job-at-a-time service for this job mix (solo step times measured per
-    lattice shape).  Served with continuous batching (shortest remaining work
-    first on the slack of a deadline guard: each job's deadline is its
-    completion time under one-job-at-a-time service in arrival order at the
-    measured solo step times, and when the earliest-deadline-first schedule
-    of the resident jobs has less than the guard's slack left, epochs serve
-    the deadline order; the guard of -0.5 s lets a job finish up to about
-    half a second plus an epoch after its deadline, which the shortest-work
-    order spends on the median; device-filling lattices and lone jobs step with
-    their tuned solo kernels) under each memory budget, and sequentially (one
-    job at a time, one lattice per launch, arrival order) on the same
-    arrivals."""
+    U{500..5000}, FP32 shifted.  The arrival rate offers 0.7 x the measured
+    batched capacity of this job mix (the server's site updates per second
+    with every job present from the start and a tenth of the steps).  Served
+    with continuous batching, shortest remaining work first (work priced by
+    the measured solo step time of each lattice shape; device-filling
+    lattices and lone jobs step with their tuned solo kernels), under each
+    memory budget, and sequentially (one job at a time, one lattice per
+    launch, arrival order) on the same arrivals."""
     import sc_inputs
     from paper_1112_5547_amd import autotune
-    from paper_1112_5547_amd.serve import (GpuBackend, Server, offered_rate, sequential_baseline,
-                                           solo_capacity, solo_step_seconds)
+    from paper_1112_5547_amd.serve import (GpuBackend, Server, batched_capacity, offered_rate,
+                                           sequential_baseline, solo_capacity, solo_step_seconds)
     probe = sc_inputs.serving_jobs(n_jobs, seed=5, rate=1.0)
-    step_s = solo_step_seconds(probe, GpuBackend("fp32_shifted"))
-    capacity = solo_capacity(probe, step_s)
-    progress(f"serving: solo capacity {capacity:.0f} MLUPS")
-    rate = offered_rate(probe, capacity, load=0.7)
-    jobs = sc_inputs.serving_jobs(n_jobs, seed=5, rate=rate)
+    be = GpuBackend("fp32_shifted")
+    step_s = solo_step_seconds(probe, be)
+    solo = solo_capacity(probe, step_s)
     # batch tile shape for the job mix, timed on the 8 smallest jobs of each
     # lattice type; the march chunks stay each lattice's own tuned chunk (a
     # chunk tuned on the smallest jobs alone can be a single-chunk march that
     # leaves the large members a few long work items per step)
-    sample = (sorted([j for j in jobs if j.lattice == 9], key=lambda j: j.sites)[:8]
-              + sorted([j for j in jobs if j.lattice == 19], key=lambda j: j.sites)[:8])
+    sample = (sorted([j for j in probe if j.lattice == 9], key=lambda j: j.sites)[:8]
+              + sorted([j for j in probe if j.lattice == 19], key=lambda j: j.sites)[:8])
     tiles = autotune.tune_batch(sample, precision="fp32_shifted", mode="fused", epoch=20,
                                 mbs=(0,))
+    capacity = batched_capacity(probe, backend=be, tiles=tiles, epoch_steps=epoch)
+    progress(f"serving: solo capacity {solo:.0f} MLUPS, batched capacity {capacity:.0f} MLUPS")
+    rate = offered_rate(probe, capacity, load=0.7)
+    jobs = sc_inputs.serving_jobs(n_jobs, seed=5, rate=rate)
     r3 = lambda v: round(v, 3) if isinstance(v, float) else v
-    be = GpuBackend("fp32_shifted")
     out = {"workload": f"{n_jobs} Poisson jobs (seed 5), 70% D2Q9 64^2-512^2 drops, 30% D3Q19 "
                        f"64^3-256^3 drops/spinodal, 500-5000 steps, FP32 shifted, offered load "
-                       f"0.7 x {capacity:.0f} MLUPS (solo service of this mix)",
-           "arrival_rate_per_s": round(rate, 4), "solo_capacity_mlups": round(capacity, 1),
+                       f"0.7 x {capacity:.0f} MLUPS (measured batched capacity of this mix)",
+           "arrival_rate_per_s": round(rate, 4), "batched_capacity_mlups": round(capacity, 1),
+           "solo_capacity_mlups": round(solo, 1),
+           "sequential_offered_load": round(0.7 * capacity / solo, 3),
            "batch_tiles": tiles, "mode": "fused", "epoch_steps": epoch, "runs": []}
     for gb in budgets_gb:
         server = Server(hbm_budget=int(gb * 1e9), epoch_steps=epoch, mode="fused", backend=be,
-                        tiles=tiles, policy="srpt", aging=0.0, guard=-0.5,
-                        nominal_rate=capacity * 1e6, step_seconds=step_s)
+                        tiles=tiles, policy="srpt", aging=0.0, nominal_rate=solo * 1e6,
+                        step_seconds=step_s)
         rep = server.run(jobs)
         served = rep.summary()
         progress(f"serving: {gb:g} GB budget: p50 {served['p50_latency_s']:.2f} s, "

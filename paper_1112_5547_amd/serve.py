@@ -406,6 +406,24 @@ def solo_capacity(jobs, step_seconds: Dict[tuple, float]) -> float:
     return work / busy / 1e6
 
 
+def batched_capacity(jobs, *, backend=None, clock=None, tiles: Optional[dict] = None,
+                     epoch_steps: int = 250, step_fraction: float = 0.1,
+                     sat_sites: int = 4_000_000) -> float:
+    """Site updates per second (in millions) of the job mix served by the
+    batching server with every job present from the start: the jobs'
+    lattices with their step counts cut to `step_fraction` (at least one
+    epoch), shortest remaining work first, total work over the time from the
+    last admission (the lattices are created first) to the last completion."""
+    short = [dataclasses.replace(j, arrival=0.0,
+                                 steps=max(epoch_steps, int(j.steps * step_fraction)))
+             for j in jobs]
+    rep = Server(hbm_budget=0, epoch_steps=epoch_steps, mode="fused", backend=backend,
+                 clock=clock, tiles=tiles, policy="srpt", sat_sites=sat_sites).run(short)
+    start = max(r.admitted for r in rep.results)
+    busy = max(r.completed for r in rep.results) - start
+    return sum(j.sites * j.steps for j in short) / busy / 1e6
+
+
 def offered_rate(jobs, capacity_mlups: float, load: float = 0.7) -> float:
     """Arrival rate (jobs/s) at which the stream offers `load` x capacity."""
     mean_work = np.mean([j.sites * j.steps for j in jobs]) / 1e6

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import sc_inputs
-from paper_1112_5547_amd.serve import Server, offered_rate
+from paper_1112_5547_amd.serve import Server, batched_capacity, offered_rate
 
 
 class SimClock:
@@ -365,3 +365,15 @@ def test_service_prices_from_solo_step_times():
                  step_seconds={(a.lattice, a.nx, a.ny, a.nz): 2e-3})
     assert srv.service_s(a, 40) == pytest.approx(40 * 2e-3)
     assert srv.service_s(b, 20) == pytest.approx(20 * b.sites / 1e4)
+
+
+def test_batched_capacity_is_the_servers_rate_on_the_whole_mix():
+    """All jobs present from the start with a tenth of their steps (at least
+    an epoch): work over the time from the last admission to the last
+    completion, which the fake device runs at its capacity plus a small cost
+    per launch."""
+    clock = SimClock()
+    be = FakeBackend(clock, capacity=1e4)
+    jobs = _jobs(12, seed=7, rate=5.0)
+    cap = batched_capacity(jobs, backend=be, clock=clock, epoch_steps=8, sat_sites=10_000)
+    assert 0.9e-2 < cap <= 1e-2          # MLUPS: 1e4 site updates per second
