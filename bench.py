@@ -431,7 +431,10 @@ def main():
         out["batched"] = batch_leg(64, args.batch_steps, epoch=250)
         progress("batch leg done")
     if not args.no_serve:
-        out["served"] = serve_leg(args.serve_jobs, budgets_gb=(96.0, 16.0), epoch=250)
+        # 96 GB holds every job that is ever resident at once; 8 GB holds one of
+        # the largest lattices (about 5.4 GB) beside small ones, so a second
+        # large job queues for memory
+        out["served"] = serve_leg(args.serve_jobs, budgets_gb=(96.0, 8.0), epoch=250)
         main_run = out["served"]["runs"][0]["served"]
         out["metric_served"] = {"p50_latency_s": main_run["p50_latency_s"],
                                 "p99_latency_s": main_run["p99_latency_s"],
