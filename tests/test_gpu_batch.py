@@ -6,8 +6,8 @@ seeded fields (Sec. 2.1 step by step): populations within 1e-12 in FP64 and
 device code as a single-lattice launch, so the alone-vs-in-the-mix comparison
 is exact equality, for FP64 and FP32-shifted members, D2Q9 and D3Q19 in one
 launch, uneven sizes, members with different step counts, members joining
-mid-run, and every compiled batch block shape with and without march-chunk
-overrides.
+mid-run, every compiled batch block shape with and without march-chunk
+overrides, and groups of D2Q9 members only at every block size.
 """
 import numpy as np
 import pytest
@@ -96,6 +96,44 @@ def test_batch_equals_solo_bitwise(mode, precision):
 # overridden ones
 BATCH_CFGS = [(256, 64, 4), (256, 32, 8), (256, 16, 16), (128, 32, 4), (512, 64, 8),
               (512, 32, 16)]
+
+
+# groups without D3Q19 members (every epoch of such a batch) at each block
+# size; one D3Q19 tile per block size
+D2Q9_TILES = {128: (32, 4), 256: (64, 4), 512: (64, 8)}
+
+
+@pytest.mark.parametrize("nt", sorted(D2Q9_TILES))
+@pytest.mark.parametrize("precision", ["fp64", "fp32_shifted"])
+def test_d2q9_only_batch_against_solo_and_oracle(nt, precision):
+    from paper_1112_5547_amd import Batch
+    members = [(k, spec) for k, spec in enumerate(SPECS) if spec[0] == 9]
+    solo = []
+    for k, spec in members:
+        say(f"solo {spec} {precision}")
+        lat = _make(spec, 100 + k, precision)
+        lat.step(spec[6])
+        solo.append(lat.get_populations())
+        lat.close()
+    say(f"D2Q9-only batch, block {nt}, {precision}")
+    b = Batch()
+    b.set_tiles(nt, *D2Q9_TILES[nt], 0, 0)
+    lats = [_make(spec, 100 + k, precision) for k, spec in members]
+    for lat, (_, spec) in zip(lats, members):
+        assert b.add(lat, spec[6])
+    for _ in range(10):
+        b.run(16, "fused")
+        if len(b.poll()) == len(lats):
+            break
+    for lat, (k, spec), ref in zip(lats, members, solo):
+        assert lat.steps_done == spec[6]
+        b.remove(lat)
+        f = lat.get_populations()
+        assert np.array_equal(f, ref), spec
+        err = maxabs(f, _oracle(spec, 100 + k))
+        assert err <= TOL[precision], (spec, err)
+        lat.close()
+    b.close()
 
 
 @pytest.mark.parametrize("cfg", BATCH_CFGS)
