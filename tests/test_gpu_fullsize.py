@@ -5,7 +5,8 @@ checked on sampled sites the oracle computes one by one (oracle.step_sites),
 and the run over many steps through properties that hold at any size (mass
 per species conserved to roundoff, lattice momentum stays zero).  The 128^3
 drop is checked the same way on a state the GPU evolved for 800 steps, where
-the interface carries the largest gradients.
+the interface carries the largest gradients, and so is the benchmark's batch of
+64 D2Q9 lattices in its fused launch.
 """
 import numpy as np
 import pytest
@@ -107,3 +108,57 @@ def test_128cube_drop_evolved_state_sampled(precision, tol):
     want = oracle.step_sites(f800, 1.0, 1.0, 1.3, sites)
     got = f801[:, :, sites].transpose(2, 0, 1)
     assert float(np.abs(got - want).max()) <= tol
+
+
+def _batch_sites(nx, ny, tx, rng, k=120):
+    """Random sites plus the lattice edges, the tile edges along x and the
+    march-chunk edges along y (chunks of 8 rows) of an nx x ny lattice."""
+    xs = [0, 1, nx - 2, nx - 1] + [x for x in (tx - 1, tx, tx + 1) if x < nx]
+    ys = [0, 7, 8, ny // 2, ny - 1]
+    edge = [y * nx + x for y in ys for x in xs]
+    return np.unique(np.concatenate([rng.integers(0, nx * ny, k), edge])).astype(np.int64)
+
+
+@pytest.mark.parametrize("tiles", [(256, 32, 8), (512, 64, 8)])
+def test_batch_of_64_lattices_sampled(tiles):
+    """The batch leg's 64 D2Q9 drop lattices (64^2-512^2, 6.87 M sites, FP32
+    shifted, per-lattice tau and G) in the fused launch, at the block shapes
+    its autotuner picks: after 20 batched steps, one more batched step equals
+    the oracle's one-site step from the batch's own state at sampled sites of
+    every member."""
+    from paper_1112_5547_amd import Batch, Lattice
+    jobs = sc_inputs.batch_jobs(64, seed=4)
+    say(f"batch of 64 D2Q9 lattices, tiles {tiles}: 20 fused steps, then one more")
+    lats = []
+    for j in jobs:
+        lat = Lattice(9, j.nx, j.ny, 1, tau_A=j.tau, G=j.G, precision="fp32_shifted")
+        fl = j.fields()
+        lat.init(fl.rho_A, fl.rho_B)
+        lats.append(lat)
+    b = Batch()
+    b.set_tiles(*tiles, 0, 0)
+    for lat in lats:
+        assert b.add(lat, 20)
+    b.run(20, "fused")
+    assert len(b.poll()) == len(lats)
+    rng = np.random.default_rng(7)
+    wants = []
+    for lat, j in zip(lats, jobs):
+        b.remove(lat)
+        f20 = lat.get_populations()
+        sites = _batch_sites(j.nx, j.ny, tiles[0], rng)
+        wants.append((sites, oracle.step_sites(f20, j.tau, j.tau, j.G, sites)))
+    for lat in lats:
+        assert b.add(lat, 1)
+    b.run(1, "fused")
+    assert len(b.poll()) == len(lats)
+    worst = 0.0
+    for lat, j, (sites, want) in zip(lats, jobs, wants):
+        b.remove(lat)
+        assert lat.steps_done == 21
+        f21 = lat.get_populations().reshape(2, 9, -1)
+        got = f21[:, :, sites].transpose(2, 0, 1)
+        worst = max(worst, float(np.abs(got - want).max()))
+        lat.close()
+    b.close()
+    assert worst <= 2e-6, worst
