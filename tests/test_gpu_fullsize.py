@@ -5,8 +5,9 @@ checked on sampled sites the oracle computes one by one (oracle.step_sites),
 and the run over many steps through properties that hold at any size (mass
 per species conserved to roundoff, lattice momentum stays zero).  The 128^3
 drop is checked the same way on a state the GPU evolved for 800 steps, where
-the interface carries the largest gradients, and so is the benchmark's batch of
-64 D2Q9 lattices in its fused launch.
+the interface carries the largest gradients, and so are the benchmark's batch of
+64 D2Q9 lattices in its fused launch and the largest lattices of its served
+job stream (ragged tiles at full size).
 """
 import numpy as np
 import pytest
@@ -162,3 +163,41 @@ def test_batch_of_64_lattices_sampled(tiles):
         lat.close()
     b.close()
     assert worst <= 2e-6, worst
+
+
+@pytest.mark.parametrize("rank", [0, 1])
+def test_largest_served_lattices_sampled(rank):
+    """The two largest D3Q19 jobs of the served stream (seed 5: a 250^3 drop
+    and a 249^3 spinodal, FP32 shifted), built as the server builds them (its
+    backend, with the autotuned solo kernel).  Their last tiles are ragged in
+    x and y: after 10 steps, one more step equals the oracle's one-site step
+    from the GPU's own state at random sites and on the tile, chunk and
+    lattice edges."""
+    from paper_1112_5547_amd.serve import GpuBackend
+    jobs = sorted((j for j in sc_inputs.serving_jobs(200, seed=5) if j.lattice == 19),
+                  key=lambda j: -j.sites)
+    job = jobs[rank]
+    n = job.nx
+    say(f"served {n}^3 {job.kind} fp32_shifted: 10 steps, then one step against the oracle")
+    be = GpuBackend("fp32_shifted")
+    lat = be.make_lattice(job)
+    _, tx, ty, mb = lat.kernel
+    lat.step(10)
+    f10 = lat.get_populations()
+    rng = np.random.default_rng(11)
+    xs = sorted({0, n - 1} | {x for k in range(1, n // tx + 1) for x in (k * tx - 1, k * tx)
+                              if x < n})
+    ys = sorted({0, n - 1} | {y for k in range(1, n // ty + 1) for y in (k * ty - 1, k * ty)
+                              if y < n})
+    zs = sorted({0, n - 1} | {z for k in range(1, n // mb + 1) for z in (k * mb - 1, k * mb)
+                              if z < n})
+    edge = [(z * n + y) * n + x for z in zs[:6] + zs[-2:] for y in ys[:2] + ys[-3:]
+            for x in xs]
+    sites = np.unique(np.concatenate([rng.integers(0, n ** 3, 3000), edge])).astype(np.int64)
+    want = oracle.step_sites(f10, job.tau, job.tau, job.G, sites)
+    del f10
+    lat.step(1)
+    f11 = lat.get_populations().reshape(2, 19, -1)
+    be.release(lat)
+    got = f11[:, :, sites].transpose(2, 0, 1)
+    assert float(np.abs(got - want).max()) <= 2e-6
