@@ -231,6 +231,17 @@ int lbm_sc_get_params(const lbm_sc *h, lbm_sc_params *p);
  * one holding the current state; for zero-copy inspection only. */
 int lbm_sc_device_buffers(const lbm_sc *h, void **buf0, void **buf1, int *current);
 
+/* Layout of those buffers (either may be NULL): the array of species s and
+ * velocity i starts at element (s Q + i) * stride, and site (x, y, z) sits at
+ * element (z ny + y) * pitch + x of it (pitch >= nx; the elements from nx to
+ * pitch of a row are padding, never read or written).  A buffer holds the
+ * post-collision populations f*_is(x, t - 1) at x, so the state is read
+ * pulled, f_is(x, t) = f*_is(x - c_i, t - 1) (eq. be of Sec. 2.1); elements
+ * are double (LBM_FP64) or float holding f - w_i rho_ref_s (LBM_FP32_SHIFTED).
+ * Lattices of 2^16 sites or more pad rows to 32 elements.  LBM_EINVAL for a
+ * NULL handle. */
+int lbm_sc_buffer_layout(const lbm_sc *h, size_t *stride, int *pitch);
+
 /* Releases the handle (NULL is a no-op).  Waits for its queued work. */
 int lbm_sc_destroy(lbm_sc *h);
 

@@ -83,6 +83,7 @@ SIGNATURES = [
     ("lbm_sc_steps_done", ctypes.c_longlong, [_P]),
     ("lbm_sc_get_params", _I, [_P, ctypes.POINTER(Params)]),
     ("lbm_sc_device_buffers", _I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _IP]),
+    ("lbm_sc_buffer_layout", _I, [_P, ctypes.POINTER(ctypes.c_size_t), _IP]),
     ("lbm_sc_destroy", _I, [_P]),
     ("lbm_sc_strerror", ctypes.c_char_p, [_I]),
     ("lbm_sc_copy_bench", _I, [_P, _P, ctypes.c_size_t, _I, _P, ctypes.POINTER(ctypes.c_float)]),

@@ -11,7 +11,9 @@
 //   f_is(x + c_i, t + 1) = f*_is(x, t)              (periodic)
 //
 // Memory layout.  Populations are SoA, one contiguous array per (species,
-// velocity): buf[(s*Q + i)*N + site], site = (z*ny + y)*nx + x.  Two buffers
+// velocity): buf[(s*Q + i)*NS + e], e = (z*ny + y)*px + x, with x rows px >= nx
+// elements apart (rows padded to 32 elements on large lattices, so that each
+// row starts on a cache line) and arrays NS >= px*ny*nz apart.  Two buffers
 // ping-pong.  A buffer holds post-collision values f*(x, t-1) at x, so the
 // state f(x, t) is read "pulled": f_is(x, t) = buf[s][i][x - c_i].  Every
 // store is aligned and coalesced; a pulled load is misaligned by at most one
@@ -148,7 +150,8 @@ struct StepParams {
     const void* src;
     void* dst;
     int NX, NY, NM;     // transverse extents and march extent
-    uint32_t P;         // plane size NX * NY
+    int PX;             // elements from one x row of a population array to the next (>= NX)
+    uint32_t P;         // elements from one plane to the next, PX * NY
     uint32_t N;         // sites
     uint32_t NS;        // elements from one population array to the next (>= N)
     int ntx, nty;       // tiles across the plane
@@ -252,6 +255,7 @@ __device__ __forceinline__ StepParams uniform_params(const StepParams& q) {
     p.NX = (int)uni32((uint32_t)q.NX);
     p.NY = (int)uni32((uint32_t)q.NY);
     p.NM = (int)uni32((uint32_t)q.NM);
+    p.PX = (int)uni32((uint32_t)q.PX);
     p.P = uni32(q.P);
     p.N = uni32(q.N);
     p.NS = uni32(q.NS);
@@ -584,7 +588,7 @@ struct TileStep {
         const int X0 = tile_x * TX, Y0 = tile_y * TY;
         const int m0 = chunk * p.mb;
         const int m1 = min(m0 + p.mb, p.NM);
-        const int NX = p.NX, NY = p.NY, NM = p.NM;
+        const int NX = p.NX, NY = p.NY, NM = p.NM, PX = p.PX;
         const uint32_t P = p.P;
 
         // interior site: frame position (tx, ty) -> periodic lattice position
@@ -597,7 +601,7 @@ struct TileStep {
             const int yy = HY ? wrapi(gy + a - HY, NY) : 0;
 #pragma unroll
             for (int b = 0; b < 3; ++b)
-                off[a][b] = (uint32_t)(yy * NX + wrapi(gx + b - 1, NX)) * (uint32_t)sizeof(T);
+                off[a][b] = (uint32_t)(yy * PX + wrapi(gx + b - 1, NX)) * (uint32_t)sizeof(T);
         }
         // ring site handled by this thread (tid < R)
         const bool ring = tid < R;
@@ -628,11 +632,11 @@ struct TileStep {
                 const int yy = HY ? wrapi(rgy + a - HY, NY) : 0;
 #pragma unroll
                 for (int b = 0; b < 3; ++b)
-                    roff[a][b] = (uint32_t)(yy * NX + wrapi(rgx + b - 1, NX)) * (uint32_t)sizeof(T);
+                    roff[a][b] = (uint32_t)(yy * PX + wrapi(rgx + b - 1, NX)) * (uint32_t)sizeof(T);
             }
         }
         const int own_fx = tx + 1, own_fy = ty + HY;
-        const uint32_t own_voff = (uint32_t)(gy * NX + gx) * (uint32_t)sizeof(T);
+        const uint32_t own_voff = (uint32_t)(gy * PX + gx) * (uint32_t)sizeof(T);
         const int ring_fx = rlx + 1, ring_fy = rly + HY;
 
         T cur[2][Q], nxt[2][Q];
@@ -791,7 +795,7 @@ struct TileStepPipe {
         const int X0 = tile_x * TX, Y0 = tile_y * TY;
         const int m0 = chunk * p.mb;
         const int m1 = min(m0 + p.mb, p.NM);
-        const int NX = p.NX, NY = p.NY, NM = p.NM;
+        const int NX = p.NX, NY = p.NY, NM = p.NM, PX = p.PX;
         const uint32_t P = p.P;
 
         const int gx = wrapi(X0 + tx, NX);
@@ -803,7 +807,7 @@ struct TileStepPipe {
             const int yy = HY ? wrapi(gy + a - HY, NY) : 0;
 #pragma unroll
             for (int b = 0; b < 3; ++b)
-                off[a][b] = (uint32_t)(yy * NX + wrapi(gx + b - 1, NX)) * (uint32_t)sizeof(T);
+                off[a][b] = (uint32_t)(yy * PX + wrapi(gx + b - 1, NX)) * (uint32_t)sizeof(T);
         }
         // ring tasks of this thread: wave task (tid / 64) + k * NW
         uint32_t roff[RPT][2 * HY + 1][3];
@@ -827,11 +831,11 @@ struct TileStepPipe {
                 const int yy = HY ? wrapi(rgy + a - HY, NY) : 0;
 #pragma unroll
                 for (int b = 0; b < 3; ++b)
-                    roff[k][a][b] = (uint32_t)(yy * NX + wrapi(rgx + b - 1, NX)) * (uint32_t)sizeof(T);
+                    roff[k][a][b] = (uint32_t)(yy * PX + wrapi(rgx + b - 1, NX)) * (uint32_t)sizeof(T);
             }
         }
         const int own_fx = tx + 1, own_fy = ty + HY;
-        const uint32_t own_voff = (uint32_t)(gy * NX + gx) * (uint32_t)sizeof(T);
+        const uint32_t own_voff = (uint32_t)(gy * PX + gx) * (uint32_t)sizeof(T);
         auto slot_of = [&](int m) { return (m - m0 + 1) & 3; };
         auto bases = [&](int m, uint32_t (&pb)[3]) {
             const int mm = wrapi(m, NM);
@@ -959,7 +963,7 @@ struct TileStepRepull {
         const int X0 = tile_x * TX, Y0 = tile_y * TY;
         const int m0 = chunk * p.mb;
         const int m1 = min(m0 + p.mb, p.NM);
-        const int NX = p.NX, NY = p.NY, NM = p.NM;
+        const int NX = p.NX, NY = p.NY, NM = p.NM, PX = p.PX;
         const uint32_t P = p.P;
 
         const int gx = wrapi(X0 + tx, NX);
@@ -971,7 +975,7 @@ struct TileStepRepull {
             const int yy = HY ? wrapi(gy + a - HY, NY) : 0;
 #pragma unroll
             for (int b = 0; b < 3; ++b)
-                off[a][b] = (uint32_t)(yy * NX + wrapi(gx + b - 1, NX)) * (uint32_t)sizeof(T);
+                off[a][b] = (uint32_t)(yy * PX + wrapi(gx + b - 1, NX)) * (uint32_t)sizeof(T);
         }
         uint32_t roff[RPT][2 * HY + 1][3];
         int rfx[RPT], rfy[RPT], rsp[RPT];
@@ -994,11 +998,11 @@ struct TileStepRepull {
                 const int yy = HY ? wrapi(rgy + a - HY, NY) : 0;
 #pragma unroll
                 for (int b = 0; b < 3; ++b)
-                    roff[k][a][b] = (uint32_t)(yy * NX + wrapi(rgx + b - 1, NX)) * (uint32_t)sizeof(T);
+                    roff[k][a][b] = (uint32_t)(yy * PX + wrapi(rgx + b - 1, NX)) * (uint32_t)sizeof(T);
             }
         }
         const int own_fx = tx + 1, own_fy = ty + HY;
-        const uint32_t own_voff = (uint32_t)(gy * NX + gx) * (uint32_t)sizeof(T);
+        const uint32_t own_voff = (uint32_t)(gy * PX + gx) * (uint32_t)sizeof(T);
         auto slot_of = [&](int m) { return (m - m0 + 1) & 3; };
         auto bases = [&](int m, uint32_t (&pb)[3]) {
             const int mm = wrapi(m, NM);
@@ -1066,6 +1070,14 @@ __device__ __forceinline__ uint32_t site_at(const SiteGeom& g, int dx, int dy, i
                                             int ny, int nz) {
     const int x = wrapi(g.x + dx, nx), y = wrapi(g.y + dy, ny), z = wrapi(g.z + dz, nz);
     return ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)nx + (uint32_t)x;
+}
+
+// The same neighbour's element in a population array whose x rows are px
+// elements apart (px >= nx; the columns from nx on are padding).
+__device__ __forceinline__ uint32_t elem_at(const SiteGeom& g, int dx, int dy, int dz, int nx,
+                                            int ny, int nz, int px) {
+    const int x = wrapi(g.x + dx, nx), y = wrapi(g.y + dy, ny), z = wrapi(g.z + dz, nz);
+    return ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)px + (uint32_t)x;
 }
 
 }  // namespace sc

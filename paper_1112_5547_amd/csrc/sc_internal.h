@@ -23,6 +23,7 @@ struct ObsArgs {
     double* u;             // u_phys [3][N] or null
     double* partial;       // [nblocks][T_COUNT]
     int nx, ny, nz;
+    int px;                // population row pitch (elements from one x row to the next)
     uint32_t N;
     uint32_t NS;           // population array stride (elements)
     double G, body_A;
@@ -82,14 +83,18 @@ using BatchPersFn = void (*)(const BatchDesc*, const WorkItem*, int, int, unsign
 hipError_t launch_step(int variant, int Q, int pol, int tx, int ty, const StepParams& p,
                        void* psi, hipStream_t s);
 bool batch_kernels(int pol, int nt, int tx19, int ty19, BatchStepFn* sf, BatchPersFn* pf);
-// Population buffers hold 2Q arrays of NS >= N elements (array (s, i) at
-// element (s Q + i) NS).
+// Population buffers hold 2Q arrays of NS >= px ny nz elements (array (s, i)
+// at element (s Q + i) NS; site (x, y, z) at element (z ny + y) px + x, with
+// x rows px >= nx elements apart).  Host-side fields (rho, u, in, out) hold
+// one element per site, (z ny + y) nx + x.
 hipError_t launch_init(int Q, int prec, void* f, uint32_t NS, const double* rho, const double* u,
-                       int nx, int ny, int nz, const double* rho_ref, hipStream_t s);
+                       int nx, int ny, int nz, int px, const double* rho_ref, hipStream_t s);
 hipError_t launch_get_plane(int Q, int prec, const void* f, uint32_t NS, double* out, int s_,
-                            int i, int nx, int ny, int nz, const double* rho_ref, hipStream_t s);
+                            int i, int nx, int ny, int nz, int px, const double* rho_ref,
+                            hipStream_t s);
 hipError_t launch_set_plane(int Q, int prec, void* f, uint32_t NS, const double* in, int s_,
-                            int i, int nx, int ny, int nz, const double* rho_ref, hipStream_t s);
+                            int i, int nx, int ny, int nz, int px, const double* rho_ref,
+                            hipStream_t s);
 hipError_t launch_observe(int Q, int prec, const ObsArgs& a, double* totals, hipStream_t s);
 int observe_blocks(uint32_t N);
 hipError_t launch_copy(void* dst, const void* src, size_t nbytes, hipStream_t s);

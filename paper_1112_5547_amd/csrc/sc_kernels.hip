@@ -78,12 +78,13 @@ bool batch_kernels(int pol, int nt, int tx19, int ty19, BatchStepFn* sf, BatchPe
 // ---------------------------------------------------------------------------
 template <int Q, class PR>
 __global__ void __launch_bounds__(256) k_init(typename PR::T* f, const double* rho, const double* u,
-                                              int nx, int ny, int nz, uint32_t N, uint32_t NS,
-                                              double rA, double rB) {
+                                              int nx, int ny, int nz, int px, uint32_t N,
+                                              uint32_t NS, double rA, double rB) {
     using T = typename PR::T;
     const uint32_t site = blockIdx.x * 256u + threadIdx.x;
     if (site >= N) return;
     const SiteGeom g = site_xyz(site, nx, ny);
+    const uint32_t e = elem_at(g, 0, 0, 0, nx, ny, nz, px);
     const double rref[2] = {rA, rB};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -101,18 +102,18 @@ __global__ void __launch_bounds__(256) k_init(typename PR::T* f, const double* r
         for (int s = 0; s < 2; ++s) {
             const double fe = VSet<Q>::w(i) * rho[(size_t)s * N + x] * poly;
             const double val = PR::shifted ? fe - VSet<Q>::w(i) * rref[s] : fe;
-            f[(size_t)(s * Q + i) * NS + site] = T(val);
+            f[(size_t)(s * Q + i) * NS + e] = T(val);
         }
     }
 }
 
 hipError_t launch_init(int Q, int prec, void* f, uint32_t NS, const double* rho, const double* u,
-                       int nx, int ny, int nz, const double* rho_ref, hipStream_t s) {
+                       int nx, int ny, int nz, int px, const double* rho_ref, hipStream_t s) {
     const uint32_t N = (uint32_t)nx * ny * nz;
     const unsigned nblk = (N + 255u) / 256u;
 #define SC_INIT(QQ, PP)                                                                      \
     hipLaunchKernelGGL((k_init<QQ, PP>), dim3(nblk), dim3(256), 0, s,                        \
-                       static_cast<typename PP::T*>(f), rho, u, nx, ny, nz, N, NS,         \
+                       static_cast<typename PP::T*>(f), rho, u, nx, ny, nz, px, N, NS,     \
                        rho_ref[0], rho_ref[1])
     if (Q == 9) {
         if (prec == 0) SC_INIT(9, PF64); else SC_INIT(9, PF32S);
@@ -130,29 +131,31 @@ hipError_t launch_init(int Q, int prec, void* f, uint32_t NS, const double* rho,
 // ---------------------------------------------------------------------------
 template <int Q, class PR>
 __global__ void __launch_bounds__(256) k_get_plane(const typename PR::T* f, double* out, int i,
-                                                   int nx, int ny, int nz, uint32_t N,
+                                                   int nx, int ny, int nz, int px, uint32_t N,
                                                    double shift) {
     const uint32_t site = blockIdx.x * 256u + threadIdx.x;
     if (site >= N) return;
     const SiteGeom g = site_xyz(site, nx, ny);
-    const uint32_t src = site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz);
+    const uint32_t src =
+        elem_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz, px);
     out[site] = (double)f[src] + shift;
 }
 
 template <int Q, class PR>
 __global__ void __launch_bounds__(256) k_set_plane(typename PR::T* f, const double* in, int i,
-                                                   int nx, int ny, int nz, uint32_t N,
+                                                   int nx, int ny, int nz, int px, uint32_t N,
                                                    double shift) {
     using T = typename PR::T;
     const uint32_t site = blockIdx.x * 256u + threadIdx.x;
     if (site >= N) return;
     const SiteGeom g = site_xyz(site, nx, ny);
     const uint32_t src = site_at(g, VSet<Q>::cx(i), VSet<Q>::cy(i), VSet<Q>::cz(i), nx, ny, nz);
-    f[site] = T(in[src] - shift);
+    f[elem_at(g, 0, 0, 0, nx, ny, nz, px)] = T(in[src] - shift);
 }
 
 hipError_t launch_get_plane(int Q, int prec, const void* f, uint32_t NS, double* out, int s_,
-                            int i, int nx, int ny, int nz, const double* rho_ref, hipStream_t s) {
+                            int i, int nx, int ny, int nz, int px, const double* rho_ref,
+                            hipStream_t s) {
     const uint32_t N = (uint32_t)nx * ny * nz;
     const unsigned nblk = (N + 255u) / 256u;
     const double wi = Q == 9 ? VSet<9>::w(i) : VSet<19>::w(i);
@@ -160,7 +163,7 @@ hipError_t launch_get_plane(int Q, int prec, const void* f, uint32_t NS, double*
 #define SC_GET(QQ, PP)                                                                        \
     hipLaunchKernelGGL((k_get_plane<QQ, PP>), dim3(nblk), dim3(256), 0, s,                    \
                        static_cast<const typename PP::T*>(f) + (size_t)(s_ * QQ + i) * NS, out,  \
-                       i, nx, ny, nz, N, shift)
+                       i, nx, ny, nz, px, N, shift)
     if (Q == 9) {
         if (prec == 0) SC_GET(9, PF64); else SC_GET(9, PF32S);
     } else {
@@ -171,7 +174,8 @@ hipError_t launch_get_plane(int Q, int prec, const void* f, uint32_t NS, double*
 }
 
 hipError_t launch_set_plane(int Q, int prec, void* f, uint32_t NS, const double* in, int s_,
-                            int i, int nx, int ny, int nz, const double* rho_ref, hipStream_t s) {
+                            int i, int nx, int ny, int nz, int px, const double* rho_ref,
+                            hipStream_t s) {
     const uint32_t N = (uint32_t)nx * ny * nz;
     const unsigned nblk = (N + 255u) / 256u;
     const double wi = Q == 9 ? VSet<9>::w(i) : VSet<19>::w(i);
@@ -179,7 +183,7 @@ hipError_t launch_set_plane(int Q, int prec, void* f, uint32_t NS, const double*
 #define SC_SET(QQ, PP)                                                                      \
     hipLaunchKernelGGL((k_set_plane<QQ, PP>), dim3(nblk), dim3(256), 0, s,                  \
                        static_cast<typename PP::T*>(f) + (size_t)(s_ * QQ + i) * NS, in, i,  \
-                       nx, ny, nz, N, shift)
+                       nx, ny, nz, px, N, shift)
     if (Q == 9) {
         if (prec == 0) SC_SET(9, PF64); else SC_SET(9, PF32S);
     } else {
@@ -201,7 +205,7 @@ hipError_t launch_set_plane(int Q, int prec, void* f, uint32_t NS, const double*
 // ---------------------------------------------------------------------------
 template <int Q, class PR>
 __global__ void __launch_bounds__(256) k_rho64(const typename PR::T* f, double* rho, int nx, int ny,
-                                               int nz, uint32_t N, uint32_t NS, double rA,
+                                               int nz, int px, uint32_t N, uint32_t NS, double rA,
                                                double rB) {
     const uint32_t site = blockIdx.x * 256u + threadIdx.x;
     if (site >= N) return;
@@ -213,7 +217,8 @@ __global__ void __launch_bounds__(256) k_rho64(const typename PR::T* f, double* 
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             r += (double)f[(size_t)(s * Q + i) * NS +
-                           site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)];
+                           elem_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz,
+                                   px)];
         rho[(size_t)s * N + site] = PR::shifted ? rref[s] + r : r;
     }
 }
@@ -274,8 +279,8 @@ __global__ void __launch_bounds__(OBS_BLOCK) k_observe(ObsArgs a) {
             for (int i = 0; i < Q; ++i) {
                 const double fv =
                     (double)f[(size_t)(s * Q + i) * a.NS +
-                              site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), a.nx,
-                                      a.ny, a.nz)];
+                              elem_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), a.nx,
+                                      a.ny, a.nz, a.px)];
                 j[0] += VSet<Q>::cx(i) * fv;
                 j[1] += VSet<Q>::cy(i) * fv;
                 j[2] += VSet<Q>::cz(i) * fv;
@@ -366,8 +371,8 @@ hipError_t launch_observe(int Q, int prec, const ObsArgs& a, double* totals, hip
 #define SC_OBS(QQ, PP)                                                                          \
     do {                                                                                        \
         hipLaunchKernelGGL((k_rho64<QQ, PP>), dim3(nblk), dim3(256), 0, s,                      \
-                           static_cast<const typename PP::T*>(a.f), rho, a.nx, a.ny, a.nz, a.N, \
-                           a.NS, a.rho_ref[0], a.rho_ref[1]);                                   \
+                           static_cast<const typename PP::T*>(a.f), rho, a.nx, a.ny, a.nz, a.px,\
+                           a.N, a.NS, a.rho_ref[0], a.rho_ref[1]);                              \
         hipLaunchKernelGGL((k_observe<QQ, PP>), dim3(nblk), dim3(OBS_BLOCK), 0, s, a);          \
     } while (0)
     if (Q == 9) {

@@ -19,7 +19,8 @@ struct lbm_sc {
     lbm_sc_params p{};
     int Q = 0;
     uint32_t N = 0;
-    uint32_t NS = 0;  // population array stride (elements), >= N
+    uint32_t NS = 0;  // population array stride (elements), >= PX ny nz
+    int PX = 0;       // population row pitch (elements), >= nx
     int device = 0;
     char* mem = nullptr;
     bool own_mem = false;
@@ -60,6 +61,7 @@ inline int sc_policy(const lbm_sc_params& p) {
 
 Layout sc_layout(const lbm_sc_params* p);
 uint32_t sc_array_stride(const lbm_sc_params* p);
+uint32_t sc_row_pitch(const lbm_sc_params* p);
 void sc_default_kernel(const lbm_sc_params* p, int* variant, int* tx, int* ty, int* mb);
 sc::StepParams sc_step_params(const lbm_sc* h, int parity);
 hipError_t sc_launch_step(lbm_sc* h, int parity, hipStream_t s);

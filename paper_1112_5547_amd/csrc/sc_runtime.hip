@@ -71,10 +71,34 @@ int validate(const lbm_sc_params* p) {
 constexpr size_t kArrayPad = 2080;
 constexpr size_t kArrayPadMinSites = size_t(1) << 16;
 
+namespace {
+
+size_t padded_stride(size_t elems, size_t sites) {
+    return (elems + 31) / 32 * 32 + (sites >= kArrayPadMinSites ? kArrayPad : 0);
+}
+
+}  // namespace
+
+// Elements from one x row of a population array to the next.  Lattices of
+// 2^16 sites or more round it up to 32 elements, so that every row starts
+// 128-byte (FP32) / 256-byte (FP64) aligned like the arrays: with rows of nx
+// elements a wave's 64 consecutive sites straddle one more cache line and
+// its stores write partial lines.  Measured on D3Q19 FP32 steps with the
+// plain row: 200^3 10,560, 216^3 11,120, 249^3 9,460 MLUPS, against 15,140
+// at 192^3 and 16,580 at 256^3 (rows of 768 and 1024 bytes).  The padding
+// columns are never written or read.  The row stays nx elements where the
+// padded arrays would leave 32-bit byte offsets.
+uint32_t sc_row_pitch(const lbm_sc_params* p) {
+    const size_t nx = (size_t)p->nx, rows = (size_t)p->ny * p->nz, N = nx * rows;
+    if (N < kArrayPadMinSites || nx % 32 == 0) return (uint32_t)nx;
+    const size_t px = (nx + 31) / 32 * 32;
+    if (padded_stride(px * rows, N) * 8 > 0xFFFFFFFFull) return (uint32_t)nx;
+    return (uint32_t)px;
+}
+
 uint32_t sc_array_stride(const lbm_sc_params* p) {
     const size_t N = (size_t)p->nx * p->ny * p->nz;
-    const size_t NS = (N + 31) / 32 * 32 + (N >= kArrayPadMinSites ? kArrayPad : 0);
-    return (uint32_t)NS;
+    return (uint32_t)padded_stride((size_t)sc_row_pitch(p) * p->ny * p->nz, N);
 }
 
 Layout sc_layout(const lbm_sc_params* p) {
@@ -149,7 +173,8 @@ StepParams sc_step_params(const lbm_sc* h, int parity) {
         sp.NY = 1;
         sp.NM = p.ny;
     }
-    sp.P = (uint32_t)sp.NX * (uint32_t)sp.NY;
+    sp.PX = h->PX;
+    sp.P = (uint32_t)sp.PX * (uint32_t)sp.NY;
     sp.N = h->N;
     sp.NS = h->NS;
     sp.ntx = (sp.NX + h->tx - 1) / h->tx;
@@ -312,6 +337,7 @@ int lbm_sc_create_ex(lbm_sc** out, const lbm_sc_params* p, void* stream, void* a
     h->Q = p->lattice;
     h->N = (uint32_t)((size_t)p->nx * p->ny * p->nz);
     h->NS = sc_array_stride(p);
+    h->PX = (int)sc_row_pitch(p);
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
         note_hip(e, "hipGetDevice");
@@ -395,7 +421,7 @@ int lbm_sc_init(lbm_sc* h, const double* rho_A, const double* rho_B, const doubl
     HIPCALL(h, hipMemcpyAsync(h->rho + N, rho_B, N * 8, hipMemcpyHostToDevice, h->stream));
     if (u) HIPCALL(h, hipMemcpyAsync(h->u, u, 3 * N * 8, hipMemcpyHostToDevice, h->stream));
     HIPCALL(h, launch_init(h->Q, h->p.precision, h->f[0], h->NS, h->rho, u ? h->u : nullptr, h->p.nx,
-                           h->p.ny, h->p.nz, h->rho_ref, h->stream));
+                           h->p.ny, h->p.nz, h->PX, h->rho_ref, h->stream));
     HIPCALL(h, hipStreamSynchronize(h->stream));
     h->cur = 0;
     h->steps = 0;
@@ -440,6 +466,7 @@ int lbm_sc_moments(lbm_sc* h, double* rho_A, double* rho_B, double* u, lbm_sc_to
     a.nx = h->p.nx;
     a.ny = h->p.ny;
     a.nz = h->p.nz;
+    a.px = h->PX;
     a.N = h->N;
     a.NS = h->NS;
     a.G = h->p.G;
@@ -507,7 +534,7 @@ int lbm_sc_get_populations(lbm_sc* h, double* f) {
     for (int s = 0; s < 2; ++s)
         for (int i = 0; i < h->Q; ++i) {
             HIPCALL(h, launch_get_plane(h->Q, h->p.precision, h->f[h->cur], h->NS, h->u, s, i, h->p.nx,
-                                        h->p.ny, h->p.nz, h->rho_ref, h->stream));
+                                        h->p.ny, h->p.nz, h->PX, h->rho_ref, h->stream));
             HIPCALL(h, hipMemcpyAsync(f + ((size_t)s * h->Q + i) * N, h->u, N * 8,
                                       hipMemcpyDeviceToHost, h->stream));
             HIPCALL(h, hipStreamSynchronize(h->stream));
@@ -540,7 +567,7 @@ int lbm_sc_set_populations(lbm_sc* h, const double* f) {
             HIPCALL(h, hipMemcpyAsync(h->u, f + ((size_t)s * h->Q + i) * N, N * 8,
                                       hipMemcpyHostToDevice, h->stream));
             HIPCALL(h, launch_set_plane(h->Q, h->p.precision, h->f[0], h->NS, h->u, s, i, h->p.nx,
-                                        h->p.ny, h->p.nz, h->rho_ref, h->stream));
+                                        h->p.ny, h->p.nz, h->PX, h->rho_ref, h->stream));
         }
     HIPCALL(h, hipStreamSynchronize(h->stream));
     h->cur = 0;
@@ -616,6 +643,13 @@ int lbm_sc_device_buffers(const lbm_sc* h, void** buf0, void** buf1, int* curren
     if (buf0) *buf0 = h->f[0];
     if (buf1) *buf1 = h->f[1];
     if (current) *current = h->cur;
+    return LBM_OK;
+}
+
+int lbm_sc_buffer_layout(const lbm_sc* h, size_t* stride, int* pitch) {
+    if (!h) return LBM_EINVAL;
+    if (stride) *stride = h->NS;
+    if (pitch) *pitch = h->PX;
     return LBM_OK;
 }
 

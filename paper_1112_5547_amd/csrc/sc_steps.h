@@ -168,8 +168,8 @@ static hipError_t launch_repull_p(int Q, int tx, int ty, const StepParams& p, hi
 
 
 // ---------------------------------------------------------------------------
-// Two-pass step: densities to an HBM psi array, then collide with a global
-// gather.  Moves (6Q + 4) values per site instead of 4Q; kept as the plain
+// Two-pass step: densities to an HBM psi array (one element per site, no row
+// padding), then collide with a global gather.  Moves (6Q + 4) values per site instead of 4Q; kept as the plain
 // form the fused kernel is measured against.
 // ---------------------------------------------------------------------------
 template <int Q, class PR>
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(256) k_density(StepParams p, typename PR::A* p
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             r += A(f[(size_t)(s * Q + i) * p.NS +
-                     site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)]);
+                     elem_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz, p.PX)]);
         psi[(size_t)s * p.N + site] = r;
     }
 }
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(256) k_collide2(StepParams p, const typename P
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             v[s][i] = f[(size_t)(s * Q + i) * p.NS +
-                        site_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz)];
+                        elem_at(g, -VSet<Q>::cx(i), -VSet<Q>::cy(i), -VSet<Q>::cz(i), nx, ny, nz, p.PX)];
     A gs[2][3];
     gather<Q>([&](int s, int i) {
         return psi[(size_t)s * p.N +
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(256) k_collide2(StepParams p, const typename P
     }, gs);
     const double body = p.body_A != 0.0 ? kolmogorov(p, g.y) : 0.0;
     collide_store<Q, PR>(v, gs, p, body, static_cast<char*>(p.dst), p.NS * (uint32_t)sizeof(T),
-                         site * (uint32_t)sizeof(T), 0u);
+                         elem_at(g, 0, 0, 0, nx, ny, nz, p.PX) * (uint32_t)sizeof(T), 0u);
 }
 
 template <int Q, class PR>

@@ -173,6 +173,20 @@ class Lattice:
         return v.value, x.value, y.value, m.value
 
     @property
+    def buffer_layout(self):
+        """(buf0, buf1, current, stride, pitch): device addresses of the two
+        population buffers, the one holding the current state, and their
+        layout (array (s, i) at element (s Q + i) stride, site (x, y, z) at
+        element (z ny + y) pitch + x of it)."""
+        b0, b1 = ctypes.c_void_p(), ctypes.c_void_p()
+        cur, pitch, stride = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        check(lib().lbm_sc_device_buffers(self._h, ctypes.byref(b0), ctypes.byref(b1),
+                                          ctypes.byref(cur)), "device_buffers")
+        check(lib().lbm_sc_buffer_layout(self._h, ctypes.byref(stride), ctypes.byref(pitch)),
+              "buffer_layout")
+        return b0.value, b1.value, cur.value, stride.value, pitch.value
+
+    @property
     def rho_ref(self):
         p = Params()
         check(lib().lbm_sc_get_params(self._h, ctypes.byref(p)), "get_params")
