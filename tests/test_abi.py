@@ -128,6 +128,35 @@ def test_population_arrays_are_padded_and_aligned():
         assert (L.lbm_sc_bytes_needed(ctypes.byref(p)) > 0) == ok
 
 
+def _layout_bytes(q, nx, ny, nz, es, px):
+    """The handle's bytes for population rows of px elements (the layout of
+    the runtime written out: 2 buffers of 2Q arrays of NS elements, then the
+    psi, rho, u, partials and totals regions, each 256-byte aligned)."""
+    al = lambda b: (b + 255) // 256 * 256
+    n = nx * ny * nz
+    ns = (px * ny * nz + 31) // 32 * 32 + (2080 if n >= 2 ** 16 else 0)
+    blocks = (n + 255) // 256
+    return (2 * al(2 * q * ns * es) + al(2 * n * es) + al(2 * n * 8) + al(3 * n * 8)
+            + al(blocks * 16 * 8) + al(16 * 8))
+
+
+def test_population_rows_are_padded_to_32_elements():
+    """From 2^16 sites on, population rows are px = nx rounded up to 32
+    elements (every row starts on a cache line); smaller lattices, rows that
+    are already a multiple of 32, and lattices whose padded arrays would
+    leave 32-bit byte offsets keep px = nx."""
+    cases = [  # (q, nx, ny, nz, es, px)
+        (9, 100, 70, 1, 8, 100),          # 7,000 sites
+        (9, 300, 230, 1, 4, 320),
+        (19, 250, 250, 250, 4, 256),
+        (19, 45, 40, 37, 8, 64),
+        (19, 64, 40, 30, 8, 64),
+        (19, 33, 4000, 4000, 4, 33),      # padded rows would pass 2^32 bytes per array
+    ]
+    for q, nx, ny, nz, es, px in cases:
+        assert _pop_bytes(q, nx, ny, nz, es) == _layout_bytes(q, nx, ny, nz, es, px), (nx, ny, nz)
+
+
 def test_tile_tables_and_strerror():
     L = _lib()
     for q in (9, 19):
