@@ -238,8 +238,8 @@ int lbm_sc_device_buffers(const lbm_sc *h, void **buf0, void **buf1, int *curren
  * post-collision populations f*_is(x, t - 1) at x, so the state is read
  * pulled, f_is(x, t) = f*_is(x - c_i, t - 1) (eq. be of Sec. 2.1); elements
  * are double (LBM_FP64) or float holding f - w_i rho_ref_s (LBM_FP32_SHIFTED).
- * Lattices of 2^16 sites or more pad rows to 32 elements.  LBM_EINVAL for a
- * NULL handle. */
+ * Lattices of 2^16 sites or more pad rows to 32 elements where the padded
+ * arrays keep 32-bit byte offsets.  LBM_EINVAL for a NULL handle. */
 int lbm_sc_buffer_layout(const lbm_sc *h, size_t *stride, int *pitch);
 
 /* Releases the handle (NULL is a no-op).  Waits for its queued work. */
