@@ -52,7 +52,7 @@ int validate(const lbm_sc_params* p) {
 
 // ---------------------------------------------------------------------------
 // Memory layout of one handle (all regions 256-byte aligned):
-//   f0, f1   : population ping-pong buffers, 2 Q N elements each
+//   f0, f1   : population ping-pong buffers, 2 Q NS elements each (rows px apart)
 //   psi      : two-pass density array, 2 N arithmetic elements
 //   rho      : FP64 densities 2 N (observables; init staging)
 //   u        : FP64 velocity 3 N (observables; init staging; population staging)
