@@ -432,7 +432,7 @@ def main():
         progress("batch leg done")
     if not args.no_serve:
         # 96 GB holds every job that is ever resident at once; 8 GB holds one of
-        # the largest lattices (about 5.4 GB) beside small ones, so a second
+        # the largest lattices (about 5.6 GB) beside small ones, so a second
         # large job queues for memory
         out["served"] = serve_leg(args.serve_jobs, budgets_gb=(96.0, 8.0), epoch=250)
         main_run = out["served"]["runs"][0]["served"]
